@@ -1,0 +1,434 @@
+"""Pins of the oracle against things other than itself (CPU only).
+
+Each check is chosen so that a plausible slip in the oracle (a dropped term,
+a wrong sign or index, a transposed operand, a wrong constant) fails it:
+published test vectors, an independent library routine, brute force on tiny
+inputs, closed forms and the exact decryption identities of the scheme.
+"""
+import ctypes
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synthdata
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- ChaCha20
+
+def _read_hex(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return bytes.fromhex("".join(l.strip() for l in f
+                                     if l.strip() and not l.startswith("#")))
+
+
+def _block(key: bytes, counter: int, nonce: bytes) -> bytes:
+    kw = (ctypes.c_uint32 * 8)(*np.frombuffer(key, dtype="<u4").tolist())
+    nw = (ctypes.c_uint32 * 3)(*np.frombuffer(nonce, dtype="<u4").tolist())
+    out = (ctypes.c_uint32 * 16)()
+    oracle.lib().oracle_chacha20_block(kw, counter, nw, out)
+    return np.array(list(out), dtype="<u4").tobytes()
+
+
+def test_chacha20_rfc8439_block_vector():
+    # RFC 8439 Section 2.3.2
+    key = bytes(range(32))
+    nonce = bytes([0, 0, 0, 9, 0, 0, 0, 0x4a, 0, 0, 0, 0])
+    assert _block(key, 1, nonce) == _read_hex("chacha20_rfc8439_s2_3_2.txt")
+
+
+def _openssl_keystream(key, counter, nonce, nbytes):
+    try:
+        lc = ctypes.CDLL("libcrypto.so.3")
+    except OSError:
+        pytest.skip("libcrypto not available")
+    lc.EVP_CIPHER_CTX_new.restype = ctypes.c_void_p
+    lc.EVP_chacha20.restype = ctypes.c_void_p
+    lc.EVP_EncryptInit_ex.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_char_p] * 2
+    lc.EVP_EncryptUpdate.argtypes = [ctypes.c_void_p, ctypes.c_char_p,
+                                     ctypes.POINTER(ctypes.c_int),
+                                     ctypes.c_char_p, ctypes.c_int]
+    lc.EVP_CIPHER_CTX_free.argtypes = [ctypes.c_void_p]
+    ctx = lc.EVP_CIPHER_CTX_new()
+    iv = counter.to_bytes(4, "little") + nonce
+    assert lc.EVP_EncryptInit_ex(ctx, lc.EVP_chacha20(), None, key, iv) == 1
+    out = ctypes.create_string_buffer(nbytes)
+    ol = ctypes.c_int(0)
+    assert lc.EVP_EncryptUpdate(ctx, out, ctypes.byref(ol), b"\0" * nbytes,
+                                nbytes) == 1
+    lc.EVP_CIPHER_CTX_free(ctx)
+    return out.raw[:ol.value]
+
+
+def test_chacha20_matches_openssl_keystream():
+    g = np.random.default_rng(7)
+    for _ in range(5):
+        key = g.integers(0, 256, 32, dtype=np.uint8).tobytes()
+        nonce = g.integers(0, 256, 12, dtype=np.uint8).tobytes()
+        ctr = int(g.integers(0, 1 << 31))
+        ks = _openssl_keystream(key, ctr, nonce, 64 * 3)
+        ours = b"".join(_block(key, ctr + b, nonce) for b in range(3))
+        assert ours == ks
+
+
+def test_mask_stream_definition():
+    """Mask j = (128-bit LE integer of words 4(j%4).. of block j//4) mod t,
+    nonce = (query id lo, query id hi, chunk); recomputed from the OpenSSL
+    keystream."""
+    key = synthdata.gen_mask_key(99)
+    qid, chunk, t, N = (5 << 32) + 17, 3, 16957441, 64
+    nonce = np.array([qid & 0xffffffff, qid >> 32, chunk], dtype="<u4").tobytes()
+    ks = _openssl_keystream(key, 0, nonce, N * 16)
+    want = [int.from_bytes(ks[16 * j:16 * j + 16], "little") % t
+            for j in range(N)]
+    got = oracle.masks(key, qid, chunk, t, N)
+    assert got.tolist() == want
+    sub = oracle.masks(key, qid, chunk, t, N, 13, 7)
+    assert sub.tolist() == want[13:20]
+
+
+# ---------------------------------------------------------------- parameters
+
+def _trial_division_prime(p: int) -> bool:
+    r = math.isqrt(p)
+    if p % 2 == 0:
+        return p == 2
+    for s in range(3, r + 1, 1 << 24):
+        cand = np.arange(s, min(r + 1, s + (1 << 24)), 2, dtype=np.int64)
+        if np.any(p % cand == 0):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("N,L,want", [
+    (4096, 2, [0x3ffffffffd6001, 0x3ffffffffd2001]),
+    (8192, 3, [0x3fffffffef8001, 0x3fffffffeb8001, 0x3fffffffe7c001]),
+])
+def test_rns_primes_are_the_largest(N, L, want):
+    got = oracle.rns_primes(N, L)
+    assert got == want
+    for q in got:
+        assert q % (2 * N) == 1 and q < (1 << 54)
+        assert _trial_division_prime(q)
+    # every other candidate = 1 mod 2N between the smallest prime and 2^54 is
+    # composite, shown by a Fermat witness
+    c = ((1 << 54) - 1) // (2 * N) * (2 * N) + 1
+    while c >= got[-1]:
+        if c not in got:
+            assert any(pow(a, c - 1, c) != 1 for a in (2, 3, 5, 7))
+        c -= 2 * N
+
+
+@pytest.mark.parametrize("N,bits,want", [(4096, 25, 16801793),
+                                         (8192, 25, 16957441),
+                                         (8192, 26, 33832961)])
+def test_plain_modulus(N, bits, want):
+    t = oracle.plain_modulus(N, bits)
+    assert t == want and t % (2 * N) == 1 and t.bit_length() == bits
+    assert _trial_division_prime(t)
+    c = (1 << (bits - 1)) + 1
+    while c < t:
+        if c % (2 * N) == 1:
+            assert any(pow(a, c - 1, c) != 1 for a in (2, 3, 5, 7))
+        c += 1
+
+
+def test_workload_params_secure_and_wide_enough():
+    for w in [synthdata.WORKLOADS[c] for c in (1, 2, 3)]:
+        P = oracle.Params.for_workload(w.N, w.L, w.t_bits)
+        assert P.security_ok()
+        maxdiff = 255 if w.dtype == "u8" else 254
+        # the bit-width rule b_d = 2 b_c + ceil(log2 d): every distance < t
+        assert w.d * maxdiff ** 2 < P.t
+        assert P.delta == P.q // P.t
+
+
+# ---------------------------------------------------------------- ring
+
+def _negacyclic_bigint(a, b, q):
+    """Dense integer product, then x^N = -1 (an independent route)."""
+    N = len(a)
+    full = [0] * (2 * N)
+    for u in range(N):
+        for v in range(N):
+            full[u + v] += int(a[u]) * int(b[v])
+    return [(full[j] - full[j + N]) % q for j in range(N)]
+
+
+@pytest.mark.parametrize("N", [1, 2, 16, 64])
+def test_negacyclic_mul_brute_force(N):
+    q = oracle.rns_primes(max(N, 2), 1)[0]
+    g = np.random.default_rng(N)
+    a = g.integers(0, q, N, dtype=np.uint64)
+    b = g.integers(0, q, N, dtype=np.uint64)
+    assert oracle.negacyclic_mul(a, b, q).tolist() == _negacyclic_bigint(a, b, q)
+    s = g.integers(-600, 600, N)
+    assert oracle.mul_small(a, s, q).tolist() == \
+        _negacyclic_bigint(a, oracle.small_mod(s, q), q)
+
+
+def test_negacyclic_monomial_is_signed_rotation():
+    N, q = 32, oracle.rns_primes(32, 1)[0]
+    a = np.random.default_rng(1).integers(0, q, N, dtype=np.uint64)
+    for j in (0, 1, 5, 31):
+        mono = np.zeros(N, dtype=np.int64)
+        mono[j] = 1
+        got = oracle.mul_small(a, mono, q)
+        want = [int(a[(u - j) % N]) if u >= j else (q - int(a[u - j + N])) % q
+                for u in range(N)]
+        assert got.tolist() == want
+
+
+def test_inner_is_sum_of_products():
+    N, d, q = 64, 5, oracle.rns_primes(64, 1)[0]
+    g = np.random.default_rng(3)
+    a = g.integers(0, q, (d, N), dtype=np.uint64)
+    gg = g.integers(-510, 1, (d, N))
+    want = [0] * N
+    for i in range(d):
+        p = _negacyclic_bigint(a[i], oracle.small_mod(gg[i], q), q)
+        want = [(x + y) % q for x, y in zip(want, p)]
+    assert oracle.inner_all(a, gg, q).tolist() == want
+    for j in (0, 17, 63):
+        assert oracle.inner_coeff(a, gg, q, j) == want[j]
+
+
+# ---------------------------------------------------------------- BFV
+
+def _toy_params(N=16, L=2, t=257):
+    return oracle.Params(N, oracle.rns_primes(N, L), t)
+
+
+def test_decrypt_of_encrypt_exhaustive_small():
+    """Dec(Enc(m)) = m for every m in Z_t, and a fresh ciphertext's noise is
+    exactly its error polynomial (c0 + c1 s = e + Delta m)."""
+    P = _toy_params()
+    s = synthdata.gen_secret(P.N, 1)
+    msgs = list(range(P.t))
+    a = synthdata.gen_uniform_a(P.qs, P.N, len(msgs), 2)
+    e = synthdata.gen_cbd_error(P.N, len(msgs), 3)
+    ct = oracle.encrypt_constants(P, s, a, e, msgs)
+    for i, m in enumerate(msgs):
+        dec = oracle.decrypt(P, ct[i], s)
+        assert dec[0] == m and all(x == 0 for x in dec[1:])
+        assert oracle.noise(P, ct[i], s, [m] + [0] * (P.N - 1)) == \
+            [int(x) for x in e[i]]
+
+
+def test_decrypt_sampled_coeffs_agree_with_full():
+    P = _toy_params(N=64, L=3, t=oracle.plain_modulus(64, 20))
+    s = synthdata.gen_secret(P.N, 4)
+    a = synthdata.gen_uniform_a(P.qs, P.N, 1, 5)
+    e = synthdata.gen_cbd_error(P.N, 1, 6)
+    ct = oracle.encrypt_constants(P, s, a, e, [12345])
+    full = oracle.phase(P, ct[0], s)
+    js = [0, 7, 63]
+    assert oracle.phase(P, ct[0], s, js) == [full[j] for j in js]
+
+
+def test_encoding_identity_plaintext():
+    """Section 4.2: sum_i f_i g_i = sum_j <q, p_j> x^j in Z_t[x]/(x^N+1) when
+    f_i is the constant q[i] and g_i carries coordinate i of every point."""
+    N, d, t = 32, 6, 65537
+    g = np.random.default_rng(11)
+    pts = g.integers(0, 256, (N, d))
+    qv = g.integers(0, 256, d)
+    acc = [0] * N
+    for i in range(d):
+        f = [int(qv[i])] + [0] * (N - 1)
+        gi = [int(pts[j, i]) for j in range(N)]
+        acc = [(x + y) % t for x, y in zip(acc, _negacyclic_bigint(f, gi, t))]
+    assert acc == [int(pts[j] @ qv) % t for j in range(N)]
+
+
+def _small_stage(n=40, d=6, N=16, L=2, t_bits=20, seed=0, dtype="u8"):
+    P = oracle.Params(N, oracle.rns_primes(N, L), oracle.plain_modulus(N, t_bits))
+    g = np.random.default_rng(seed)
+    if dtype == "u8":
+        pts = g.integers(0, 256, (n, d)).astype(np.uint8)
+        qv = g.integers(0, 256, d).astype(np.uint8)
+    else:
+        pts = g.integers(-127, 128, (n, d)).astype(np.int8)
+        qv = g.integers(-127, 128, d).astype(np.int8)
+    s = synthdata.gen_secret(N, seed + 1)
+    a = synthdata.gen_uniform_a(P.qs, N, d, seed + 2)
+    e = synthdata.gen_cbd_error(N, d, seed + 3)
+    ct = oracle.encrypt_constants(P, s, a, e, [int(x) for x in qv])
+    perm = synthdata.gen_perm(n, seed + 4)
+    slot = oracle.slot_map_linear(n, N, perm)
+    key = synthdata.gen_mask_key(seed + 5)
+    return P, pts, qv, s, ct, slot, key
+
+
+@pytest.mark.parametrize("dtype", ["u8", "i8"])
+def test_share_sum_is_squared_distance(dtype):
+    """[client + server]_t = ||q - p||^2 for every real slot (closed form),
+    padding slots decrypt to their mask only, and the noise obeys the bound
+    d N eta max|g| + (q mod t)(d max|g| + 2): the product's integer message
+    W = sum_i [q_i]_t g_i + [P - r]_t is W = M + tK with |K| <= d max|g| + 2,
+    and Delta t K = -(q mod t) K mod q."""
+    P, pts, qv, s, ct, slot, key = _small_stage(dtype=dtype)
+    n, d = pts.shape
+    C = len(slot) // P.N
+    qn2 = int((qv.astype(np.int64) ** 2).sum()) % P.t
+    maxg = 2 * int(np.abs(pts.astype(np.int64)).max())
+    bound = d * P.N * 21 * maxg + (P.q % P.t) * (d * maxg + 2)
+    dist = ((pts.astype(np.int64) - qv.astype(np.int64)) ** 2).sum(axis=1)
+    for k in range(C):
+        g, nrm = oracle.chunk_plaintexts(pts, slot, P.N, k)
+        out, r = oracle.server_chunk(P, ct, g, nrm, key, 77, k)
+        cs = oracle.client_shares(P, out, s, qn2)
+        ids = slot[k * P.N:(k + 1) * P.N]
+        for j in range(P.N):
+            tot = (int(cs[j]) + int(r[j])) % P.t
+            if ids[j] >= 0:
+                assert tot == dist[ids[j]]
+            else:
+                assert tot == qn2
+        # noise of the product ciphertext against the message [V + P - r]_t
+        V = [(-2 * int(pts[i].astype(np.int64) @ qv.astype(np.int64))
+              if i >= 0 else 0) for i in ids]
+        msg = [(V[j] + int(nrm[j]) - int(r[j])) % P.t for j in range(P.N)]
+        v = oracle.noise(P, out, s, msg)
+        assert max(abs(x) for x in v) <= bound < P.delta // 2
+        # sampled coefficients agree with the full chunk
+        js = [0, 3, P.N - 1]
+        sc, sr = oracle.server_coeffs(P, ct, g, nrm, key, 77, k, js)
+        assert (sc == out[:, :, js]).all() and (sr == r[js]).all()
+
+
+def test_server_plaintext_lift_is_signed():
+    """The plaintext of a point is -2p as a signed integer (not its Z_t
+    representative): with a zero secret and zero error, c0 of the product is
+    exactly Delta * sum_i m_i (-2 p_i) + Delta [||p||^2 - r]_t mod q_l."""
+    P, pts, qv, s, ct, slot, key = _small_stage(n=16, d=3)
+    zero_s = np.zeros(P.N, dtype=np.int8)
+    a = np.zeros((3, P.L, P.N), dtype=np.uint64)
+    e = np.zeros((3, P.N), dtype=np.int16)
+    ct0 = oracle.encrypt_constants(P, zero_s, a, e, [int(x) for x in qv])
+    g, nrm = oracle.chunk_plaintexts(pts, slot, P.N, 0)
+    out, r = oracle.server_chunk(P, ct0, g, nrm, key, 1, 0)
+    for j in range(P.N):
+        pid = slot[j]
+        V = -2 * int(pts[pid].astype(np.int64) @ qv.astype(np.int64))
+        M = (int(nrm[j]) - int(r[j])) % P.t
+        for l, ql in enumerate(P.qs):
+            assert int(out[0, l, j]) == (P.delta * V + P.delta * M) % ql
+            assert int(out[1, l, j]) == 0
+
+
+# ---------------------------------------------------------------- top-k
+
+def test_naive_topk_matches_sort():
+    """Algorithm 1 returns the k smallest values in sorted order.  With
+    distinct values the (value, ID) list is unique and equals a sort; with
+    ties only the values are unique, so the IDs are checked for validity."""
+    g = np.random.default_rng(5)
+    distinct = g.permutation(400).tolist()
+    ids = list(range(400))
+    for k in (1, 3, 10, 400):
+        v, i = oracle.naive_topk(distinct, ids, k)
+        assert list(zip(v, i)) == sorted(zip(distinct, ids))[:k]
+    vals = g.integers(0, 50, 400).tolist()
+    for k in (1, 3, 10, 400):
+        v, i = oracle.naive_topk(vals, ids, k)
+        assert v == sorted(vals)[:k]
+        assert len(set(i)) == k and all(vals[x] == y for x, y in zip(i, v))
+
+
+def test_approx_topk_special_cases():
+    g = np.random.default_rng(6)
+    vals = g.permutation(1000)
+    ids = np.arange(1000)
+    # l = n: every bin is one item -> exact top-k
+    assert oracle.approx_topk(vals, ids, 10, 1000) == oracle.naive_topk(
+        vals.tolist(), ids.tolist(), 10)
+    # k = 1: the global minimum is always its bin's minimum
+    for l in (1, 7, 100):
+        assert oracle.approx_topk(vals, ids, 1, l)[0] == [0]
+    with pytest.raises(ValueError):
+        oracle.approx_topk(vals, ids, 11, 10)
+    assert oracle.bin_bounds(10, 3) == [(0, 4), (4, 7), (7, 10)]
+
+
+def _closed_forms(n, l, k):
+    b = n // l
+    e_hit = l * (1 - math.comb(n - b, k) / math.comb(n, k))
+    p_exact = 1.0
+    for j in range(k):
+        p_exact *= (n - j * b) / (n - j)
+    return e_hit, p_exact
+
+
+def test_approx_topk_brute_force_n16():
+    """n=16, l=4, k=2: enumerate every placement of the two smallest values."""
+    n, l, k = 16, 4, 2
+    hits, exact, cnt = 0, 0, 0
+    for p0, p1 in itertools.permutations(range(n), 2):
+        vals = np.full(n, 100)
+        rest = iter(range(2, n))
+        for j in range(n):
+            vals[j] = 0 if j == p0 else 1 if j == p1 else next(rest) + 10
+        v, _ = oracle.approx_topk(vals, np.arange(n), k, l)
+        inter = len({0, 1} & set(v))
+        hits += inter
+        exact += inter == 2
+        cnt += 1
+    e_hit, p_exact = _closed_forms(n, l, k)
+    assert hits / cnt == pytest.approx(1.8) == pytest.approx(e_hit)
+    assert exact / cnt == pytest.approx(0.8) == pytest.approx(p_exact)
+
+
+def test_approx_topk_monte_carlo_matches_closed_form():
+    """Theorems 1-2 (proofs in the appendix): with distinct values a true
+    top-k item is returned iff it is the minimum of its bin, so |I| is the
+    number of bins that hold at least one of the top k:
+    E|I| = l(1 - C(n-n/l,k)/C(n,k)), P(exact) = prod_j (n - j n/l)/(n - j)."""
+    n, l, k, T = 1000, 100, 10, 4000
+    g = np.random.default_rng(8)
+    base = np.arange(n)
+    hits = np.empty(T)
+    exact = np.empty(T)
+    for it in range(T):
+        vals = g.permutation(base)
+        v, _ = oracle.approx_topk(vals, base, k, l)
+        inter = len(set(range(k)) & set(v))
+        hits[it] = inter
+        exact[it] = inter == k
+    e_hit, p_exact = _closed_forms(n, l, k)
+    se_h = hits.std() / math.sqrt(T)
+    se_p = math.sqrt(p_exact * (1 - p_exact) / T)
+    assert abs(hits.mean() - e_hit) < 4 * se_h + 1e-9
+    assert abs(exact.mean() - p_exact) < 4 * se_p
+    # the workload values quoted for l=100 / l=1000
+    assert _closed_forms(10_000, 100, 10)[0] == pytest.approx(9.566, abs=1e-3)
+    assert _closed_forms(10 ** 6, 1000, 10)[1] == pytest.approx(0.956, abs=1e-3)
+
+
+def test_sqdist_matches_numpy():
+    g = np.random.default_rng(9)
+    pts = g.integers(-127, 128, (300, 96)).astype(np.int8)
+    qv = g.integers(-127, 128, 96).astype(np.int8)
+    want = ((pts.astype(np.int64) - qv.astype(np.int64)) ** 2).sum(axis=1)
+    assert (oracle.sqdist(qv, pts) == want).all()
+
+
+# ---------------------------------------------------------------- packing
+
+def test_packing_matches_paper_communication():
+    """d query ciphertexts up and ceil(n/N) result ciphertexts down, each
+    2 N log2(q) bits at N = 2^13, log2 q = 180, lands within 10% of the
+    communication the paper reports for its linear scan."""
+    with open(os.path.join(GOLD, "paper_comm_linear_scan.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    N, logq = 8192, 180
+    for name, n, d, mb in rows:
+        n, d, mb = int(n), int(d), float(mb)
+        cts = d + -(-n // N)
+        ours = cts * 2 * N * logq / 8 / 1e6
+        assert abs(ours - mb) / mb < 0.10, name
