@@ -1,0 +1,255 @@
+/*
+ * sanns.h -- C ABI of the MI355X homomorphic distance stage of secure
+ * approximate k-NN search (SANNS, Chen et al.).
+ *
+ * The stage (Section 4.2 "Distance Computation via AHE"; linear-scan protocol,
+ * steps 2-4): the client sends d BFV ciphertexts c_i, each encrypting the
+ * constant polynomial q'[i] over R_q = Z_q[x]/(x^N + 1), q = q_0 ... q_{L-1}
+ * (RNS primes).  The server holds its n points packed N per chunk, coordinate
+ * i of chunk k as the plaintext polynomial g_{i,k}, and returns for every
+ * chunk
+ *         f_k = sum_i c_i * g_{i,k}  +  Delta [ ||p||^2 - r ]_t
+ * with r uniform in Z_t.  Decrypting f_k gives the client
+ * [-2 <q,p> + ||p||^2 - r]_t per slot, so client share [Dec + ||q||^2]_t and
+ * server share r add up to ||q - p||^2 mod t (Section 2.1 arithmetic shares).
+ *
+ * Conventions (all entry points):
+ *   - Every call returns sanns_status; SANNS_OK is 0, errors are negative and
+ *     sanns_last_error() returns a message for the calling thread.
+ *   - Argument errors found on the host return before anything is enqueued.
+ *   - "dev" pointers are HIP device memory owned by the caller; the library
+ *     never frees caller memory.  "host" pointers are read before return.
+ *   - All device work is enqueued on the caller's stream (hipStream_t passed
+ *     as void*; NULL is the null stream).  Inputs must stay alive and
+ *     unmodified until the stream reaches the end of the call's work.
+ *   - Ciphertexts cross the boundary in coefficient form with every residue
+ *     in [0, q_l).  Layout of one ciphertext: [2][L][N] uint64 (component,
+ *     limb, coefficient).  The NTT form is internal.
+ *   - Shares are uint32 in [0, t).
+ *   - A context may be used from several host threads only with distinct
+ *     streams and distinct output and workspace buffers.
+ */
+#ifndef SANNS_H
+#define SANNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SANNS_OK = 0,
+    SANNS_E_INVALID = -1,   /* null pointer, zero or oversized dimension     */
+    SANNS_E_PARAMS = -2,    /* parameter set rejected (see sanns_ctx_create)  */
+    SANNS_E_RANGE = -3,     /* input value outside its documented range       */
+    SANNS_E_WORKSPACE = -4, /* caller's buffer smaller than the size queried  */
+    SANNS_E_DEVICE = -5,    /* HIP runtime error (message has the HIP text)   */
+    SANNS_E_NOMEM = -6      /* device allocation for internal tables failed   */
+} sanns_status;
+
+#define SANNS_MAX_LIMBS 4
+#define SANNS_MAX_D 4096
+
+/* Parameter flags. */
+#define SANNS_FLAG_INSECURE_TEST 1u /* allow N < 1024 or log2 q above the
+                                       128-bit cap (tests only)            */
+
+/* BFV parameters (Section 2.3; Section 5 "Parameters").
+ *   N    ring degree, power of two, 16 <= N <= 16384
+ *   L    number of RNS primes, 1 <= L <= SANNS_MAX_LIMBS
+ *   q    distinct primes, q_l < 2^54, q_l = 1 mod 2N
+ *   t    plaintext modulus, 2 <= t < 2^31, coprime to every q_l
+ *   flags SANNS_FLAG_* */
+typedef struct {
+    uint32_t N;
+    uint32_t L;
+    uint64_t q[SANNS_MAX_LIMBS];
+    uint64_t t;
+    uint32_t flags;
+} sanns_params;
+
+/* Point coordinate types accepted by sanns_encode_db. */
+#define SANNS_U8 0
+#define SANNS_I8 1
+
+/* Execution forms of sanns_distances. */
+#define SANNS_MODE_PLAIN 0   /* one kernel launch per ciphertext operation    */
+#define SANNS_MODE_FUSED 1   /* fused NTT / multiply-accumulate / INTT+mask   */
+#define SANNS_MODE_BATCHED 2 /* fused kernels replayed from a cached hipGraph */
+
+typedef struct sanns_ctx sanns_ctx;
+
+/* Resident database descriptor (non-owning).  The buffer `mem` holds, in
+ * this order:
+ *   residues [L][n_chunks][d][N] of 8 bytes: the NTT form of g_{i,k} mod q_l,
+ *            stored as two 27-bit halves (low half in the first 32-bit word);
+ *   norms    [n_chunks][N] uint32: ||p||^2 of the point in each slot (0 for
+ *            padding slots).
+ * Size: sanns_db_bytes(). */
+typedef struct {
+    void *mem;
+    size_t bytes;
+    uint32_t n_chunks;
+    uint32_t d;
+} sanns_db;
+
+/* ------------------------------------------------------------------------
+ * Context and parameters
+ * ---------------------------------------------------------------------- */
+
+/* Derive the default parameter set for ring degree N (Section 5
+ * "Parameters"; the workloads fix N, L and the width of t):
+ *   q_l  = the L largest primes below 2^54 with q_l = 1 mod 2N, descending;
+ *   t    = the smallest prime >= 2^(t_bits-1) with t = 1 mod 2N.
+ * out: host.  Errors: SANNS_E_INVALID (null, N not a power of two in
+ * [16, 16384], L outside [1, SANNS_MAX_LIMBS], t_bits outside [2, 31]). */
+sanns_status sanns_params_derive(uint32_t N, uint32_t L, uint32_t t_bits,
+                                 sanns_params *out);
+
+/* Create a context on HIP device `device`: checks the parameters (primality,
+ * q_l = 1 mod 2N, t coprime to q, log2 q at most the 128-bit-security cap
+ * 27/54/109/218/438 bits for N = 1024..16384 unless SANNS_FLAG_INSECURE_TEST)
+ * and uploads the twiddle tables and constants.  *out receives the context.
+ * Errors: SANNS_E_INVALID, SANNS_E_PARAMS, SANNS_E_DEVICE, SANNS_E_NOMEM. */
+sanns_status sanns_ctx_create(const sanns_params *p, int device,
+                              sanns_ctx **out);
+
+/* Release the context's device tables and cached graphs.  NULL is a no-op.
+ * The caller must have synchronised every stream the context was used on. */
+void sanns_ctx_destroy(sanns_ctx *ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *sanns_last_error(void);
+
+/* Copy the context's parameters to *out (host). */
+sanns_status sanns_ctx_params(const sanns_ctx *ctx, sanns_params *out);
+
+/* ------------------------------------------------------------------------
+ * Server: database encoding (linear-scan protocol steps 1 and 3)
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of a resident database with n_chunks chunks of dimension d. */
+size_t sanns_db_bytes(const sanns_ctx *ctx, uint32_t n_chunks, uint32_t d);
+
+/* Encode the server's points (Section 4.2; linear-scan protocol, steps 1
+ * and 3): slot j of chunk k holds point slot_point[kN + j] (the server's
+ * random permutation, or a cluster layout), -1 marking a padding slot.  For
+ * every (limb l, chunk k, coordinate i) the plaintext g_{i,k}[j] = -2 p[i] of
+ * the slot's point (0 for padding), taken as a signed integer, is lifted mod
+ * q_l and transformed to NTT form; norms[k][j] = ||p||^2.
+ *   points      dev [n][d], uint8 (SANNS_U8) or int8 (SANNS_I8), row-major
+ *   slot_point  dev [n_chunks * N] int64, each -1 or in [0, n)
+ *   db          descriptor: mem (dev) of at least sanns_db_bytes(), n_chunks
+ *               and d filled in by the caller
+ * A slot index outside [-1, n) is encoded as padding and sets the device
+ * error word (sanns_device_status).  Errors: SANNS_E_INVALID (null, d = 0 or > SANNS_MAX_D,
+ * n_chunks = 0), SANNS_E_WORKSPACE (db->bytes too small), SANNS_E_RANGE
+ * (d * max|coordinate difference|^2 >= t), SANNS_E_DEVICE. */
+sanns_status sanns_encode_db(sanns_ctx *ctx, const void *points, int dtype,
+                             uint64_t n, const int64_t *slot_point,
+                             const sanns_db *db, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Client (test helpers): encryption and decryption
+ * ---------------------------------------------------------------------- */
+
+/* Symmetric BFV encryption of constants (Section 2.3 private-key AHE;
+ * linear-scan protocol step 2): for each query qi < Q and coordinate i < d,
+ *   c1 = a,   c0 = -a*s + e + Delta [msg]_t  (Delta = floor(q/t); the
+ *   constant sits in coefficient 0), every limb l reduced mod q_l.
+ *   sk      dev [N] int8 in {-1, 0, 1}
+ *   msgs    dev [Q][d] int32 (any sign; reduced mod t)
+ *   a       dev [Q][d][L][N] uint64, a[..][l][..] in [0, q_l)
+ *   e       dev [Q][d][N] int16
+ *   ct_out  dev [Q][d][2][L][N] uint64, coefficient form
+ * The randomness (sk, a, e) is an input: the caller draws it.  Errors:
+ * SANNS_E_INVALID, SANNS_E_DEVICE. */
+sanns_status sanns_encrypt_query(sanns_ctx *ctx, const int8_t *sk,
+                                 const int32_t *msgs, uint32_t Q, uint32_t d,
+                                 const uint64_t *a, const int16_t *e,
+                                 uint64_t *ct_out, void *stream);
+
+/* Client decryption to shares (linear-scan protocol steps 4-5): for each of
+ * the M ciphertexts, x = c0 + c1*s mod q (exact CRT over the limbs),
+ * m = floor((t x + floor(q/2)) / q) mod t, and
+ *   client_share[m][j] = [m_j + qnorm2[m]]_t.
+ *   sk            dev [N] int8
+ *   ct            dev [M][2][L][N] uint64, residues in [0, q_l)
+ *   qnorm2        dev [M] uint32 = [||q||^2]_t of each ciphertext's query, or
+ *                 NULL to return the decrypted message m itself
+ *   client_share  dev [M][N] uint32
+ * Errors: SANNS_E_INVALID, SANNS_E_DEVICE. */
+sanns_status sanns_decrypt_shares(sanns_ctx *ctx, const int8_t *sk,
+                                  const uint64_t *ct, uint32_t M,
+                                  const uint32_t *qnorm2,
+                                  uint32_t *client_share, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Server hot path: distances to secret shares
+ * ---------------------------------------------------------------------- */
+
+/* Work description: output m < M is the pair (query work[2m], chunk
+ * work[2m+1]), work a host array [M][2] uint32 read before the call
+ * returns.  work == NULL means every chunk for every query in query-major
+ * order (M = Q * n_chunks, m = q * n_chunks + k). */
+
+/* Bytes of device workspace sanns_distances needs for Q queries and M
+ * outputs in the given mode. */
+size_t sanns_distances_workspace(const sanns_ctx *ctx, const sanns_db *db,
+                                 uint32_t Q, uint32_t M, int mode);
+
+/* The server's distance stage (Section 4.2; linear-scan protocol step 3,
+ * with the norm and mask folded into the ciphertext): for each output m with
+ * (query qi, chunk k),
+ *   ct_out[m]       = sum_i c_{qi,i} * g_{i,k}  +  Delta [ ||p||^2 - r ]_t
+ *   server_share[m] = r
+ * where r[j] is the ChaCha20 mask of slot j: key = mask_key (32 bytes read as
+ * 8 little-endian words), nonce = (query_ids[qi] low word, high word, k),
+ * block counter j/4, and r[j] = (128-bit little-endian integer of block words
+ * 4(j%4)..4(j%4)+3) mod t.  A (mask_key, query id) pair must never be reused
+ * for different queries.
+ *   ct_in         dev [Q][d][2][L][N] uint64, coefficient form, residues
+ *                 < q_l (checked on the device; a violation sets the error
+ *                 word read by sanns_device_status and the outputs are
+ *                 undefined)
+ *   mask_key      host [32]
+ *   query_ids     dev [Q] uint64
+ *   work          host [M][2] uint32 or NULL (see above); entries outside
+ *                 Q x n_chunks are rejected with SANNS_E_RANGE
+ *   mode          SANNS_MODE_PLAIN, SANNS_MODE_FUSED or SANNS_MODE_BATCHED;
+ *                 all three give bit-identical outputs
+ *   ct_out        dev [M][2][L][N] uint64, coefficient form
+ *   server_share  dev [M][N] uint32
+ *   workspace     dev, at least sanns_distances_workspace() bytes
+ * SANNS_MODE_BATCHED captures the launches into a hipGraph cached in the
+ * context under the call's pointers and sizes and replays it on later calls
+ * with the same ones (new contents of every device buffer, query_ids
+ * included, are picked up; the mask_key bytes are part of the cache key).  Errors: SANNS_E_INVALID,
+ * SANNS_E_WORKSPACE, SANNS_E_DEVICE. */
+sanns_status sanns_distances(sanns_ctx *ctx, const sanns_db *db,
+                             const uint64_t *ct_in, uint32_t Q,
+                             const uint8_t *mask_key,
+                             const uint64_t *query_ids,
+                             const uint32_t *work, uint32_t M, int mode,
+                             uint64_t *ct_out, uint32_t *server_share,
+                             void *workspace, size_t ws_bytes, void *stream);
+
+/* Synchronise `stream` and return (and clear) the context's device error
+ * word: SANNS_E_RANGE if, since the last call, an input residue was >= q_l
+ * or a slot index of sanns_encode_db was outside [-1, n) (such a slot is
+ * encoded as padding). */
+sanns_status sanns_device_status(sanns_ctx *ctx, void *stream);
+
+/* Fix the register tile of the multiply-accumulate kernel to qt queries x
+ * ct chunks (the built shapes are 1x1, 1x2, 1x4, 1x8, 2x2, 2x4, 4x2, 2x3,
+ * 3x2); qt = ct = 0 restores the automatic choice.  Used by the autotuner.
+ * Errors: SANNS_E_INVALID for a shape that is not built. */
+sanns_status sanns_set_schedule(sanns_ctx *ctx, int qt, int ct);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SANNS_H */

@@ -1,0 +1,773 @@
+// HIP kernels of the homomorphic distance stage (gfx950).
+//
+// Data layouts (all device memory):
+//   ciphertexts        [.][2][L][N] uint64, coefficient form, residues < q_l
+//   query NTT form     [Q][d][2][L][N] uint64 (bit-reversed NTT order)
+//   database residues  [L][C][d][N] uint2: 27-bit halves of the NTT form
+//   database norms     [C][N] uint32
+//   server shares      [M][N] uint32
+#include <hip/hip_runtime.h>
+#include "kernels.h"
+#include "launch.h"
+#include "ntt.h"
+
+namespace sanns {
+
+// --------------------------------------------------------------------------
+// helpers
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ const uint64_t* tw_fwd(const TwSet& T, int l, int N) {
+  return T.tw[l];
+}
+__device__ __forceinline__ const uint64_t* twp_fwd(const TwSet& T, int l, int N) {
+  return T.tw[l] + N;
+}
+__device__ __forceinline__ const uint64_t* tw_inv(const TwSet& T, int l, int N) {
+  return T.tw[l] + 2 * N;
+}
+__device__ __forceinline__ const uint64_t* twp_inv(const TwSet& T, int l, int N) {
+  return T.tw[l] + 3 * N;
+}
+
+// General product of two residues (Karatsuba on 27-bit halves, then the
+// same fold as the multiply-accumulate).
+__device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, const Prime& P) {
+  uint32_t a0, a1, b0, b1;
+  split27(a, a0, a1);
+  split27(b, b0, b1);
+  Acc3 acc;
+  acc.lo = mul32x32(a0, b0);
+  acc.hi = mul32x32(a1, b1);
+  acc.mid = mul32x32(a0 + a1, b0 + b1);
+  return acc3_reduce(acc, P);
+}
+
+// Move residues held at the last forward pass's positions to the first
+// inverse pass's positions (through LDS).
+__device__ __forceinline__ void remap_fwd_to_inv(uint64_t (&v)[16], uint64_t* lds, int logN,
+                                                 int tid) {
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 16; ++a) lds[lds_pad(fwd_last_index(tid, a, logN))] = v[a];
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 16; ++a) v[a] = lds[lds_pad(inv_first_index(tid, a, logN))];
+}
+
+__device__ __forceinline__ void reduce4q(uint64_t (&v)[16], uint64_t q) {
+#pragma unroll
+  for (int a = 0; a < 16; ++a) v[a] = csub(csub(v[a], 2 * q), q);
+}
+
+__device__ __forceinline__ void scale_ninv(uint64_t (&v)[16], const Prime& P) {
+#pragma unroll
+  for (int a = 0; a < 16; ++a) v[a] = shoup(v[a], P.ninv, P.ninvp, P.q);
+}
+
+// --------------------------------------------------------------------------
+// forward / inverse transforms of independent polynomials
+// --------------------------------------------------------------------------
+
+// One polynomial per workgroup; polynomial p uses limb p % L.
+__global__ void __launch_bounds__(1024)
+k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int logN, int L,
+          PrimeSet ps, TwSet tws, uint32_t* err) {
+  extern __shared__ uint64_t lds[];
+  const int tid = threadIdx.x, N = 1 << logN;
+  const int p = blockIdx.x, l = p % L;
+  const Prime& P = ps.p[l];
+  const uint64_t* src = in + (size_t)p * N;
+  uint64_t v[16];
+  bool bad = false;
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    v[a] = src[fwd_first_index(tid, a, logN)];
+    bad |= v[a] >= P.q;
+  }
+  if (bad && err) atomicOr(err, 1u);
+  ntt_fwd(v, lds, logN, tid, tw_fwd(tws, l, N), twp_fwd(tws, l, N), P.q);
+  reduce4q(v, P.q);
+  uint64_t* dst = out + (size_t)p * N;
+#pragma unroll
+  for (int a = 0; a < 16; ++a) dst[fwd_last_index(tid, a, logN)] = v[a];
+}
+
+// In-place inverse transform, result multiplied by N^-1 and in [0, q).
+__global__ void __launch_bounds__(1024)
+k_ntt_inv(uint64_t* __restrict__ io, int logN, int L, PrimeSet ps, TwSet tws) {
+  extern __shared__ uint64_t lds[];
+  const int tid = threadIdx.x, N = 1 << logN;
+  const int p = blockIdx.x, l = p % L;
+  const Prime& P = ps.p[l];
+  uint64_t* buf = io + (size_t)p * N;
+  uint64_t v[16];
+#pragma unroll
+  for (int a = 0; a < 16; ++a) v[a] = buf[inv_first_index(tid, a, logN)];
+  ntt_inv(v, lds, logN, tid, tw_inv(tws, l, N), twp_inv(tws, l, N), P.q);
+  scale_ninv(v, P);
+  __syncthreads();  // every thread has read its inputs before any overwrite
+#pragma unroll
+  for (int a = 0; a < 16; ++a) buf[inv_last_index(tid, a, logN)] = v[a];
+}
+
+// --------------------------------------------------------------------------
+// server masks: ChaCha20 (RFC 8439 block function), four slots per block
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t rotl(uint32_t x, int n) {
+  return __builtin_rotateleft32(x, n);
+}
+
+#define SANNS_QR(a, b, c, d)          \
+  a += b; d ^= a; d = rotl(d, 16);    \
+  c += d; b ^= c; b = rotl(b, 12);    \
+  a += b; d ^= a; d = rotl(d, 8);     \
+  c += d; b ^= c; b = rotl(b, 7);
+
+__device__ __forceinline__ void chacha_block(const MaskKey& K, uint32_t ctr, uint32_t n0,
+                                             uint32_t n1, uint32_t n2, uint32_t (&o)[16]) {
+  uint32_t x0 = 0x61707865u, x1 = 0x3320646eu, x2 = 0x79622d32u, x3 = 0x6b206574u;
+  uint32_t x4 = K.k[0], x5 = K.k[1], x6 = K.k[2], x7 = K.k[3];
+  uint32_t x8 = K.k[4], x9 = K.k[5], x10 = K.k[6], x11 = K.k[7];
+  uint32_t x12 = ctr, x13 = n0, x14 = n1, x15 = n2;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    SANNS_QR(x0, x4, x8, x12) SANNS_QR(x1, x5, x9, x13)
+    SANNS_QR(x2, x6, x10, x14) SANNS_QR(x3, x7, x11, x15)
+    SANNS_QR(x0, x5, x10, x15) SANNS_QR(x1, x6, x11, x12)
+    SANNS_QR(x2, x7, x8, x13) SANNS_QR(x3, x4, x9, x14)
+  }
+  o[0] = x0 + 0x61707865u; o[1] = x1 + 0x3320646eu;
+  o[2] = x2 + 0x79622d32u; o[3] = x3 + 0x6b206574u;
+  o[4] = x4 + K.k[0]; o[5] = x5 + K.k[1]; o[6] = x6 + K.k[2]; o[7] = x7 + K.k[3];
+  o[8] = x8 + K.k[4]; o[9] = x9 + K.k[5]; o[10] = x10 + K.k[6]; o[11] = x11 + K.k[7];
+  o[12] = x12 + ctr; o[13] = x13 + n0; o[14] = x14 + n1; o[15] = x15 + n2;
+}
+#undef SANNS_QR
+
+// (w3 2^96 + w2 2^64 + w1 2^32 + w0) mod t by Horner steps below 2^63.
+__device__ __forceinline__ uint32_t mod_t_128(uint32_t w0, uint32_t w1, uint32_t w2,
+                                              uint32_t w3, uint32_t t, uint64_t tone) {
+  uint64_t r = reduce64(w3, tone, t);
+  r = reduce64((r << 32) | w2, tone, t);
+  r = reduce64((r << 32) | w1, tone, t);
+  r = reduce64((r << 32) | w0, tone, t);
+  return (uint32_t)r;
+}
+
+__device__ __forceinline__ void work_pair(const uint32_t* work, int m, int C, int& qi, int& k) {
+  if (work) {
+    qi = (int)work[2 * m];
+    k = (int)work[2 * m + 1];
+  } else {
+    qi = m / C;
+    k = m % C;
+  }
+}
+
+// Thread per (output m, block b): masks of slots 4b .. 4b+3.
+__global__ void __launch_bounds__(256)
+k_masks(MaskKey K, const uint64_t* __restrict__ qids, const uint32_t* __restrict__ work,
+        int C, int M, int N, uint32_t t, uint64_t tone, uint32_t* __restrict__ share) {
+  const int nb = N >> 2;
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= (long)M * nb) return;
+  const int m = (int)(g / nb), b = (int)(g % nb);
+  int qi, k;
+  work_pair(work, m, C, qi, k);
+  const uint64_t id = qids[qi];
+  uint32_t o[16];
+  chacha_block(K, (uint32_t)b, (uint32_t)id, (uint32_t)(id >> 32), (uint32_t)k, o);
+  uint4 r;
+  r.x = mod_t_128(o[0], o[1], o[2], o[3], t, tone);
+  r.y = mod_t_128(o[4], o[5], o[6], o[7], t, tone);
+  r.z = mod_t_128(o[8], o[9], o[10], o[11], t, tone);
+  r.w = mod_t_128(o[12], o[13], o[14], o[15], t, tone);
+  reinterpret_cast<uint4*>(share + (size_t)m * N)[b] = r;
+}
+
+// --------------------------------------------------------------------------
+// inverse transform of the products plus the norm-and-mask plaintext
+// --------------------------------------------------------------------------
+
+// Polynomial p = (m 2 + c) L + l of ct_out: INTT, times N^-1, and for c = 0
+// add Delta_l [norm - r]_t at every coefficient.
+__global__ void __launch_bounds__(1024)
+k_intt_mask(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
+            const uint32_t* __restrict__ norms, const uint32_t* __restrict__ work, int C,
+            int logN, int L, uint32_t t, PrimeSet ps, TwSet tws) {
+  extern __shared__ uint64_t lds[];
+  const int tid = threadIdx.x, N = 1 << logN;
+  const int p = blockIdx.x, l = p % L, c = (p / L) & 1, m = p / (2 * L);
+  const Prime& P = ps.p[l];
+  uint64_t* buf = ct + (size_t)p * N;
+  uint64_t v[16];
+#pragma unroll
+  for (int a = 0; a < 16; ++a) v[a] = buf[inv_first_index(tid, a, logN)];
+  ntt_inv(v, lds, logN, tid, tw_inv(tws, l, N), twp_inv(tws, l, N), P.q);
+  scale_ninv(v, P);
+  if (c == 0) {
+    int qi, k;
+    work_pair(work, m, C, qi, k);
+    const uint32_t* nrm = norms + (size_t)k * N;
+    const uint32_t* r = share + (size_t)m * N;
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      const int j = inv_last_index(tid, a, logN);
+      const uint32_t pn = nrm[j], rj = r[j];
+      const uint64_t mv = pn >= rj ? pn - rj : pn + t - rj;
+      v[a] = addmod(v[a], shoup(mv, P.delta, P.deltap, P.q), P.q);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 16; ++a) buf[inv_last_index(tid, a, logN)] = v[a];
+}
+
+// --------------------------------------------------------------------------
+// fused multiply-accumulate over the resident database
+// --------------------------------------------------------------------------
+
+// Thread = one slot of one limb; it accumulates the QT x CT (query, chunk)
+// pairs of its tile for both ciphertext components over all d coordinates.
+// Without a tile table the schedule is every query against every chunk:
+// tile y covers queries (y / ceil(C/CT)) QT .. and chunks (y mod ceil(C/CT)) CT ..,
+// clamped to the last query / chunk with the clamped pairs not written.
+template <int QT, int CT>
+__device__ __forceinline__ MacTile<QT, CT> regular_tile(int y, int Q, int C) {
+  MacTile<QT, CT> T;
+  const int ncg = (C + CT - 1) / CT;
+  const int q0 = (y / ncg) * QT, k0 = (y % ncg) * CT;
+#pragma unroll
+  for (int a = 0; a < QT; ++a) T.q[a] = q0 + a < Q ? q0 + a : Q - 1;
+#pragma unroll
+  for (int b = 0; b < CT; ++b) T.k[b] = k0 + b < C ? k0 + b : C - 1;
+#pragma unroll
+  for (int a = 0; a < QT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b)
+      T.out[a][b] = (q0 + a < Q && k0 + b < C) ? (q0 + a) * C + k0 + b : -1;
+  return T;
+}
+
+template <int QT, int CT>
+__global__ void __launch_bounds__(256)
+k_mac(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db,
+      const MacTile<QT, CT>* __restrict__ tiles, int Q, int d, int L, int logN, int C,
+      PrimeSet ps, uint64_t* __restrict__ out) {
+  const int N = 1 << logN;
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int l = blockIdx.z;
+  const MacTile<QT, CT> T = tiles ? tiles[blockIdx.y] : regular_tile<QT, CT>(blockIdx.y, Q, C);
+  const Prime& P = ps.p[l];
+  const size_t qstride_i = (size_t)2 * L * N;                 // next coordinate
+  const size_t dbstride_i = (size_t)N;
+  const uint64_t* qb[QT];
+  const uint2* dbb[CT];
+#pragma unroll
+  for (int a = 0; a < QT; ++a) qb[a] = qntt + ((size_t)T.q[a] * d * 2 * L + l) * N + s;
+#pragma unroll
+  for (int b = 0; b < CT; ++b) dbb[b] = db + (((size_t)l * C + T.k[b]) * d) * N + s;
+
+  uint64_t res[QT][2][CT];
+#pragma unroll
+  for (int a = 0; a < QT; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < CT; ++b) res[a][c][b] = 0;
+
+  for (int i0 = 0; i0 < d; i0 += 255) {
+    const int i1 = d - i0 < 255 ? d : i0 + 255;
+    Acc3 acc[QT][2][CT];
+#pragma unroll
+    for (int a = 0; a < QT; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < CT; ++b) acc3_zero(acc[a][c][b]);
+    for (int i = i0; i < i1; ++i) {
+      uint32_t x0[QT][2], x1[QT][2], x01[QT][2];
+#pragma unroll
+      for (int a = 0; a < QT; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const uint64_t x = qb[a][i * qstride_i + (size_t)c * L * N];
+          split27(x, x0[a][c], x1[a][c]);
+          x01[a][c] = x0[a][c] + x1[a][c];
+        }
+#pragma unroll
+      for (int b = 0; b < CT; ++b) {
+        const uint2 y = dbb[b][i * dbstride_i];
+        const uint32_t y01 = y.x + y.y;
+#pragma unroll
+        for (int a = 0; a < QT; ++a)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            acc[a][c][b].lo += mul32x32(x0[a][c], y.x);
+            acc[a][c][b].hi += mul32x32(x1[a][c], y.y);
+            acc[a][c][b].mid += mul32x32(x01[a][c], y01);
+          }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < QT; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < CT; ++b)
+          res[a][c][b] = addmod(res[a][c][b], acc3_reduce(acc[a][c][b], P), P.q);
+  }
+#pragma unroll
+  for (int a = 0; a < QT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      const int o = T.out[a][b];
+      if (o < 0) continue;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) out[(((size_t)o * 2 + c) * L + l) * N + s] = res[a][c][b];
+    }
+}
+
+// --------------------------------------------------------------------------
+// database encoding
+// --------------------------------------------------------------------------
+
+// Thread per slot: gathers the slot's point into the transposed plaintext
+// buffer gt[k][i][j] = -2 p[i] (int16) and writes [||p||^2] to norms.
+// Slots [base, base + total) of the database; gt is local to that range.
+__global__ void __launch_bounds__(256)
+k_gather(const uint8_t* __restrict__ pts, int is_signed, long n, int d,
+         const int64_t* __restrict__ slot_point, long base, long total, int logN,
+         int16_t* __restrict__ gt, uint32_t* __restrict__ norms, uint32_t* err) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int N = 1 << logN;
+  const long k = g >> logN;
+  const int j = (int)(g & (N - 1));
+  long pid = slot_point[base + g];
+  if (pid >= n || pid < -1) {
+    if (err) atomicOr(err, 2u);
+    pid = -1;
+  }
+  int16_t* col = gt + (size_t)k * d * N + j;
+  uint32_t nrm = 0;
+  if (pid < 0) {
+    for (int i = 0; i < d; ++i) col[(size_t)i * N] = 0;
+  } else {
+    const uint8_t* row = pts + (size_t)pid * d;
+    for (int i = 0; i < d; ++i) {
+      const int x = is_signed ? (int)(int8_t)row[i] : (int)row[i];
+      col[(size_t)i * N] = (int16_t)(-2 * x);
+      nrm += (uint32_t)(x * x);
+    }
+  }
+  norms[base + g] = nrm;
+}
+
+// Workgroup per (l, k, i) with k in [k0, k0 + nk): lift the signed
+// plaintext row mod q_l, forward NTT, store as 27-bit halves.
+__global__ void __launch_bounds__(1024)
+k_encode_ntt(const int16_t* __restrict__ gt, uint2* __restrict__ dbres, int k0, int nk, int C,
+             int d, int logN, int L, PrimeSet ps, TwSet tws) {
+  extern __shared__ uint64_t lds[];
+  const int tid = threadIdx.x, N = 1 << logN;
+  const long bl = blockIdx.x;  // (l nk + k - k0) d + i
+  const int l = (int)(bl / ((long)nk * d));
+  const long ki = bl % ((long)nk * d);
+  const long b = ((long)l * C + k0) * d + ki;
+  const Prime& P = ps.p[l];
+  const int16_t* src = gt + (size_t)ki * N;
+  uint64_t v[16];
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    const int x = src[fwd_first_index(tid, a, logN)];
+    v[a] = x < 0 ? P.q - (uint64_t)(-x) : (uint64_t)x;
+  }
+  ntt_fwd(v, lds, logN, tid, tw_fwd(tws, l, N), twp_fwd(tws, l, N), P.q);
+  reduce4q(v, P.q);
+  uint2* dst = dbres + (size_t)b * N;
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    uint2 y;
+    split27(v[a], y.x, y.y);
+    dst[fwd_last_index(tid, a, logN)] = y;
+  }
+}
+
+// --------------------------------------------------------------------------
+// client helpers: secret key transform, encryption, decryption
+// --------------------------------------------------------------------------
+
+// Workgroup per limb: NTT of the ternary secret lifted mod q_l.
+__global__ void __launch_bounds__(1024)
+k_sk_ntt(const int8_t* __restrict__ sk, uint64_t* __restrict__ out, int logN, PrimeSet ps,
+         TwSet tws) {
+  extern __shared__ uint64_t lds[];
+  const int tid = threadIdx.x, N = 1 << logN, l = blockIdx.x;
+  const Prime& P = ps.p[l];
+  uint64_t v[16];
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    const int x = sk[fwd_first_index(tid, a, logN)];
+    v[a] = x < 0 ? P.q - (uint64_t)(-x) : (uint64_t)x;
+  }
+  ntt_fwd(v, lds, logN, tid, tw_fwd(tws, l, N), twp_fwd(tws, l, N), P.q);
+  reduce4q(v, P.q);
+#pragma unroll
+  for (int a = 0; a < 16; ++a) out[(size_t)l * N + fwd_last_index(tid, a, logN)] = v[a];
+}
+
+// Workgroup per (query, coordinate, limb): c1 = a, c0 = -a s + e + Delta m.
+__global__ void __launch_bounds__(1024)
+k_encrypt(const uint64_t* __restrict__ a_in, const int16_t* __restrict__ e_in,
+          const int32_t* __restrict__ msgs, const uint64_t* __restrict__ sk_ntt,
+          uint64_t* __restrict__ ct, int L, int logN, uint32_t t, PrimeSet ps, TwSet tws) {
+  extern __shared__ uint64_t lds[];
+  const int tid = threadIdx.x, N = 1 << logN;
+  const int b = blockIdx.x;  // (qi d + i) L + l
+  const int l = b % L;
+  const int qd = b / L;      // qi d + i
+  const Prime& P = ps.p[l];
+  const uint64_t* a = a_in + (size_t)b * N;
+  uint64_t v[16];
+#pragma unroll
+  for (int x = 0; x < 16; ++x) v[x] = a[fwd_first_index(tid, x, logN)];
+  ntt_fwd(v, lds, logN, tid, tw_fwd(tws, l, N), twp_fwd(tws, l, N), P.q);
+  reduce4q(v, P.q);
+#pragma unroll
+  for (int x = 0; x < 16; ++x)
+    v[x] = mulmod(v[x], sk_ntt[(size_t)l * N + fwd_last_index(tid, x, logN)], P);
+  remap_fwd_to_inv(v, lds, logN, tid);
+  ntt_inv(v, lds, logN, tid, tw_inv(tws, l, N), twp_inv(tws, l, N), P.q);
+  scale_ninv(v, P);
+  // message [m]_t as a constant: Delta m in coefficient 0
+  const int64_t mraw = msgs[qd];
+  int64_t mm = mraw % (int64_t)t;
+  if (mm < 0) mm += t;
+  const uint64_t dm = shoup((uint64_t)mm, P.delta, P.deltap, P.q);
+  const int16_t* e = e_in + (size_t)qd * N;
+  uint64_t* c0 = ct + ((size_t)qd * 2 * L + l) * N;
+  uint64_t* c1 = ct + (((size_t)qd * 2 + 1) * L + l) * N;
+#pragma unroll
+  for (int x = 0; x < 16; ++x) {
+    const int j = inv_last_index(tid, x, logN);
+    const int ej = e[j];
+    const uint64_t ev = ej < 0 ? P.q - (uint64_t)(-ej) : (uint64_t)ej;
+    uint64_t r = submod(ev, v[x], P.q);
+    if (j == 0) r = addmod(r, dm, P.q);
+    c0[j] = r;
+  }
+  for (int j = tid; j < N; j += blockDim.x) c1[j] = a[j];
+}
+
+// Multi-word helpers for the exact CRT decode (little-endian 32-bit words).
+__device__ __forceinline__ void mw_addmul(uint32_t (&z)[kMaxWords], const uint32_t* m,
+                                          uint32_t b, int shift_words, int words) {
+  uint64_t carry = 0;
+  for (int w = 0; w + shift_words < kMaxWords; ++w) {
+    const uint32_t mw = w < words ? m[w] : 0u;
+    const uint64_t cur = (uint64_t)z[w + shift_words] + (uint64_t)mw * b + carry;
+    z[w + shift_words] = (uint32_t)cur;
+    carry = cur >> 32;
+  }
+}
+
+// z >= y ?
+__device__ __forceinline__ bool mw_geq(const uint32_t (&z)[kMaxWords],
+                                       const uint32_t (&y)[kMaxWords]) {
+  bool gt = false, eq = true;
+  for (int w = kMaxWords - 1; w >= 0; --w) {
+    if (eq) {
+      if (z[w] > y[w]) { gt = true; eq = false; }
+      else if (z[w] < y[w]) { eq = false; }
+    }
+  }
+  return gt || eq;
+}
+
+__device__ __forceinline__ void mw_sub(uint32_t (&z)[kMaxWords], const uint32_t (&y)[kMaxWords]) {
+  int64_t borrow = 0;
+  for (int w = 0; w < kMaxWords; ++w) {
+    const int64_t cur = (int64_t)z[w] - (int64_t)y[w] - borrow;
+    z[w] = (uint32_t)cur;
+    borrow = cur < 0 ? 1 : 0;
+  }
+}
+
+// m = round(t x / q) mod t for x given by its residues xl (exact):
+//   y_l = x_l (q/q_l)^-1 mod q_l,  y_l t = A_l q_l + B_l,
+//   t x / q = sum_l A_l + sum_l B_l / q_l  (mod t),
+//   round(sum_l B_l / q_l) = floor((2 Z + q) / 2q),  Z = sum_l B_l (q / q_l).
+__device__ __forceinline__ uint32_t crt_round(const uint64_t* xl, int L, const PrimeSet& ps,
+                                              const DecodeConst& D) {
+  uint32_t Z[kMaxWords];
+#pragma unroll
+  for (int w = 0; w < kMaxWords; ++w) Z[w] = 0;
+  uint64_t sumA = 0;
+  for (int l = 0; l < L; ++l) {
+    const Prime& P = ps.p[l];
+    const uint64_t y = shoup(xl[l], D.inv[l], D.invp[l], P.q);
+    uint64_t A = mulhi64(y, D.tqp[l]);
+    uint64_t B = mullo64(y, D.tq[l]) - mullo64(A, P.q);
+    if (B >= P.q) { B -= P.q; A += 1; }
+    sumA += A;
+    mw_addmul(Z, D.Mw[l], (uint32_t)B, 0, D.words);
+    mw_addmul(Z, D.Mw[l], (uint32_t)(B >> 32), 1, D.words);
+  }
+  // W = 2 Z + q
+  uint32_t W[kMaxWords], twoq[kMaxWords];
+  uint64_t carry = 0, c2 = 0;
+  for (int w = 0; w < kMaxWords; ++w) {
+    const uint64_t z2 = ((uint64_t)Z[w] << 1) | c2;
+    c2 = (uint64_t)Z[w] >> 31;
+    const uint64_t cur = (z2 & 0xffffffffull) + D.qw[w] + carry;
+    W[w] = (uint32_t)cur;
+    carry = cur >> 32;
+    const uint64_t q2 = ((uint64_t)D.qw[w] << 1);
+    twoq[w] = (uint32_t)q2 | (w ? (D.qw[w - 1] >> 31) : 0u);
+  }
+  uint32_t rnd = 0;
+  for (int l = 0; l < L; ++l) {
+    if (mw_geq(W, twoq)) {
+      mw_sub(W, twoq);
+      rnd += 1;
+    }
+  }
+  return (uint32_t)((sumA + rnd) % D.t);
+}
+
+// Workgroup per ciphertext: x_l = INTT(NTT(c1) NTT(s)) + c0 per limb, then the
+// exact decode and the client share [m + ||q||^2]_t.
+__global__ void __launch_bounds__(1024)
+k_decrypt(const uint64_t* __restrict__ ct, const uint64_t* __restrict__ sk_ntt,
+          const uint32_t* __restrict__ qnorm2, uint32_t* __restrict__ outp, int L, int logN,
+          PrimeSet ps, TwSet tws, DecodeConst D) {
+  extern __shared__ uint64_t lds[];
+  const int tid = threadIdx.x, N = 1 << logN, m = blockIdx.x;
+  uint64_t x[kMaxLimbs][16];
+  for (int l = 0; l < L; ++l) {
+    const Prime& P = ps.p[l];
+    const uint64_t* c0 = ct + (((size_t)m * 2) * L + l) * N;
+    const uint64_t* c1 = ct + (((size_t)m * 2 + 1) * L + l) * N;
+    uint64_t v[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a) v[a] = c1[fwd_first_index(tid, a, logN)];
+    ntt_fwd(v, lds, logN, tid, tw_fwd(tws, l, N), twp_fwd(tws, l, N), P.q);
+    reduce4q(v, P.q);
+#pragma unroll
+    for (int a = 0; a < 16; ++a)
+      v[a] = mulmod(v[a], sk_ntt[(size_t)l * N + fwd_last_index(tid, a, logN)], P);
+    remap_fwd_to_inv(v, lds, logN, tid);
+    ntt_inv(v, lds, logN, tid, tw_inv(tws, l, N), twp_inv(tws, l, N), P.q);
+    scale_ninv(v, P);
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      const uint64_t r = addmod(v[a], c0[inv_last_index(tid, a, logN)], P.q);
+#pragma unroll
+      for (int ll = 0; ll < kMaxLimbs; ++ll)
+        if (ll == l) x[ll][a] = r;
+    }
+  }
+  const uint32_t qn = qnorm2 ? qnorm2[m] : 0u;
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    uint64_t xl[kMaxLimbs];
+#pragma unroll
+    for (int l = 0; l < kMaxLimbs; ++l) xl[l] = x[l][a];
+    const uint32_t mm = crt_round(xl, L, ps, D);
+    const uint64_t s = (uint64_t)mm + qn;
+    outp[(size_t)m * N + inv_last_index(tid, a, logN)] = (uint32_t)(s >= D.t ? s - D.t : s);
+  }
+}
+
+// --------------------------------------------------------------------------
+// plain form: one launch per ciphertext operation
+// --------------------------------------------------------------------------
+
+// tmp[c][l][j] = c_hat_i[c][l][j] g_hat_{i,k}[l][j]  (one query coordinate)
+__global__ void __launch_bounds__(256)
+k_mult_plain(const uint64_t* __restrict__ cq, const uint2* __restrict__ db, int i, int k,
+             int d, int C, int L, int logN, PrimeSet ps, uint64_t* __restrict__ tmp) {
+  const int N = 1 << logN;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 2 * L * N) return;
+  const int j = g & (N - 1), l = (g >> logN) % L;
+  const Prime& P = ps.p[l];
+  const uint2 y = db[(((size_t)l * C + k) * d + i) * N + j];
+  const uint64_t b = ((uint64_t)y.y << 27) | y.x;
+  tmp[g] = mulmod(cq[g], b, P);
+}
+
+// acc[c][l][j] += tmp[c][l][j]
+__global__ void __launch_bounds__(256)
+k_add(uint64_t* __restrict__ acc, const uint64_t* __restrict__ tmp, int L, int logN,
+      PrimeSet ps) {
+  const int N = 1 << logN;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= 2 * L * N) return;
+  const int l = (g >> logN) % L;
+  acc[g] = addmod(acc[g], tmp[g], ps.p[l].q);
+}
+
+// c0[l][j] += Delta_l [norm_j - r_j]_t   (coefficient form)
+__global__ void __launch_bounds__(256)
+k_add_plain(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
+            const uint32_t* __restrict__ norms, int k, int L, int logN, uint32_t t,
+            PrimeSet ps) {
+  const int N = 1 << logN;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= L * N) return;
+  const int j = g & (N - 1), l = g >> logN;
+  const Prime& P = ps.p[l];
+  const uint32_t pn = norms[(size_t)k * N + j], rj = share[j];
+  const uint64_t mv = pn >= rj ? pn - rj : pn + t - rj;
+  ct[g] = addmod(ct[g], shoup(mv, P.delta, P.deltap, P.q), P.q);
+}
+
+// --------------------------------------------------------------------------
+// host launchers
+// --------------------------------------------------------------------------
+
+static inline size_t ntt_lds_bytes(int logN) {
+  const int N = 1 << logN;
+  return (size_t)(N + (N >> 4) + 1) * sizeof(uint64_t);
+}
+
+hipError_t launch_ntt_fwd(const uint64_t* in, uint64_t* out, int n_polys, int logN, int L,
+                          const PrimeSet& ps, const TwSet& tws, uint32_t* err,
+                          hipStream_t st) {
+  if (n_polys <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ntt_fwd, dim3(n_polys), dim3(1 << (logN - 4)), ntt_lds_bytes(logN),
+                     st, in, out, logN, L, ps, tws, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_ntt_inv(uint64_t* io, int n_polys, int logN, int L, const PrimeSet& ps,
+                          const TwSet& tws, hipStream_t st) {
+  if (n_polys <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ntt_inv, dim3(n_polys), dim3(1 << (logN - 4)), ntt_lds_bytes(logN),
+                     st, io, logN, L, ps, tws);
+  return hipGetLastError();
+}
+
+hipError_t launch_masks(const MaskKey& K, const uint64_t* qids, const uint32_t* work, int C,
+                        int M, int logN, uint32_t t, uint64_t tone, uint32_t* share,
+                        hipStream_t st) {
+  const long total = (long)M * ((1 << logN) >> 2);
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_masks, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, K,
+                     qids, work, C, M, 1 << logN, t, tone, share);
+  return hipGetLastError();
+}
+
+hipError_t launch_intt_mask(uint64_t* ct, const uint32_t* share, const uint32_t* norms,
+                            const uint32_t* work, int C, int M, int logN, int L, uint32_t t,
+                            const PrimeSet& ps, const TwSet& tws, hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_intt_mask, dim3(M * 2 * L), dim3(1 << (logN - 4)),
+                     ntt_lds_bytes(logN), st, ct, share, norms, work, C, logN, L, t, ps,
+                     tws);
+  return hipGetLastError();
+}
+
+template <int QT, int CT>
+static hipError_t launch_mac_t(const uint64_t* qntt, const uint2* db, const void* tiles,
+                               int n_tiles, int Q, int d, int L, int logN, int C,
+                               const PrimeSet& ps, uint64_t* out, hipStream_t st) {
+  const int N = 1 << logN;
+  const int bs = N < 256 ? N : 256;
+  dim3 grid(N / bs, n_tiles, L);
+  hipLaunchKernelGGL((k_mac<QT, CT>), grid, dim3(bs), 0, st, qntt, db,
+                     (const MacTile<QT, CT>*)tiles, Q, d, L, logN, C, ps, out);
+  return hipGetLastError();
+}
+
+size_t mac_tile_bytes(int QT, int CT) {
+#define SANNS_MAC_SIZE(a, b) \
+  if (QT == a && CT == b) return sizeof(MacTile<a, b>);
+  SANNS_MAC_SHAPES(SANNS_MAC_SIZE)
+#undef SANNS_MAC_SIZE
+  return 0;
+}
+
+hipError_t launch_mac(int QT, int CT, const uint64_t* qntt, const uint2* db, const void* tiles,
+                      int n_tiles, int Q, int d, int L, int logN, int C, const PrimeSet& ps,
+                      uint64_t* out, hipStream_t st) {
+  if (n_tiles <= 0) return hipSuccess;
+#define SANNS_MAC_CASE(a, b) \
+  if (QT == a && CT == b)    \
+    return launch_mac_t<a, b>(qntt, db, tiles, n_tiles, Q, d, L, logN, C, ps, out, st);
+  SANNS_MAC_SHAPES(SANNS_MAC_CASE)
+#undef SANNS_MAC_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_gather(const void* pts, int is_signed, long n, int d,
+                         const int64_t* slot_point, long base, long total, int logN,
+                         int16_t* gt, uint32_t* norms, uint32_t* err, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     (const uint8_t*)pts, is_signed, n, d, slot_point, base, total, logN, gt,
+                     norms, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_ntt(const int16_t* gt, uint2* dbres, int k0, int nk, int C, int d,
+                             int logN, int L, const PrimeSet& ps, const TwSet& tws,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_encode_ntt, dim3((unsigned)((long)L * nk * d)), dim3(1 << (logN - 4)),
+                     ntt_lds_bytes(logN), st, gt, dbres, k0, nk, C, d, logN, L, ps, tws);
+  return hipGetLastError();
+}
+
+hipError_t launch_sk_ntt(const int8_t* sk, uint64_t* out, int logN, int L, const PrimeSet& ps,
+                         const TwSet& tws, hipStream_t st) {
+  hipLaunchKernelGGL(k_sk_ntt, dim3(L), dim3(1 << (logN - 4)), ntt_lds_bytes(logN), st, sk,
+                     out, logN, ps, tws);
+  return hipGetLastError();
+}
+
+hipError_t launch_encrypt(const uint64_t* a, const int16_t* e, const int32_t* msgs,
+                          const uint64_t* sk_ntt, uint64_t* ct, int Qd, int L, int logN,
+                          uint32_t t, const PrimeSet& ps, const TwSet& tws, hipStream_t st) {
+  hipLaunchKernelGGL(k_encrypt, dim3(Qd * L), dim3(1 << (logN - 4)), ntt_lds_bytes(logN), st,
+                     a, e, msgs, sk_ntt, ct, L, logN, t, ps, tws);
+  return hipGetLastError();
+}
+
+hipError_t launch_decrypt(const uint64_t* ct, int M, const uint64_t* sk_ntt,
+                          const uint32_t* qnorm2, uint32_t* out, int L, int logN,
+                          const PrimeSet& ps, const TwSet& tws, const DecodeConst& D,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_decrypt, dim3(M), dim3(1 << (logN - 4)), ntt_lds_bytes(logN), st, ct,
+                     sk_ntt, qnorm2, out, L, logN, ps, tws, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_mult_plain(const uint64_t* cq, const uint2* db, int i, int k, int d, int C,
+                             int L, int logN, const PrimeSet& ps, uint64_t* tmp,
+                             hipStream_t st) {
+  const int total = 2 * L * (1 << logN);
+  hipLaunchKernelGGL(k_mult_plain, dim3((total + 255) / 256), dim3(256), 0, st, cq, db, i, k,
+                     d, C, L, logN, ps, tmp);
+  return hipGetLastError();
+}
+
+hipError_t launch_add(uint64_t* acc, const uint64_t* tmp, int L, int logN, const PrimeSet& ps,
+                      hipStream_t st) {
+  const int total = 2 * L * (1 << logN);
+  hipLaunchKernelGGL(k_add, dim3((total + 255) / 256), dim3(256), 0, st, acc, tmp, L, logN,
+                     ps);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_plain(uint64_t* ct, const uint32_t* share, const uint32_t* norms, int k,
+                            int L, int logN, uint32_t t, const PrimeSet& ps, hipStream_t st) {
+  const int total = L * (1 << logN);
+  hipLaunchKernelGGL(k_add_plain, dim3((total + 255) / 256), dim3(256), 0, st, ct, share,
+                     norms, k, L, logN, t, ps);
+  return hipGetLastError();
+}
+
+}  // namespace sanns

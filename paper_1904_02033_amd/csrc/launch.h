@@ -1,0 +1,50 @@
+// Host-side launchers of the kernels in kernels.hip.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "kernels.h"
+
+namespace sanns {
+
+// (QT, CT) register tiles of the multiply-accumulate kernel that are built.
+#define SANNS_MAC_SHAPES(X) \
+  X(1, 1) X(1, 2) X(1, 4) X(1, 8) X(2, 2) X(2, 4) X(4, 2) X(2, 3) X(3, 2)
+
+hipError_t launch_ntt_fwd(const uint64_t* in, uint64_t* out, int n_polys, int logN, int L,
+                          const PrimeSet& ps, const TwSet& tws, uint32_t* err, hipStream_t st);
+hipError_t launch_ntt_inv(uint64_t* io, int n_polys, int logN, int L, const PrimeSet& ps,
+                          const TwSet& tws, hipStream_t st);
+hipError_t launch_masks(const MaskKey& K, const uint64_t* qids, const uint32_t* work, int C,
+                        int M, int logN, uint32_t t, uint64_t tone, uint32_t* share,
+                        hipStream_t st);
+hipError_t launch_intt_mask(uint64_t* ct, const uint32_t* share, const uint32_t* norms,
+                            const uint32_t* work, int C, int M, int logN, int L, uint32_t t,
+                            const PrimeSet& ps, const TwSet& tws, hipStream_t st);
+// tiles == NULL: every query against every chunk (Q x C outputs, m = q C + k).
+hipError_t launch_mac(int QT, int CT, const uint64_t* qntt, const uint2* db, const void* tiles,
+                      int n_tiles, int Q, int d, int L, int logN, int C, const PrimeSet& ps,
+                      uint64_t* out, hipStream_t st);
+size_t mac_tile_bytes(int QT, int CT);  // 0 for a shape that is not built
+hipError_t launch_gather(const void* pts, int is_signed, long n, int d,
+                         const int64_t* slot_point, long base, long total, int logN,
+                         int16_t* gt, uint32_t* norms, uint32_t* err, hipStream_t st);
+hipError_t launch_encode_ntt(const int16_t* gt, uint2* dbres, int k0, int nk, int C, int d,
+                             int logN, int L, const PrimeSet& ps, const TwSet& tws,
+                             hipStream_t st);
+hipError_t launch_sk_ntt(const int8_t* sk, uint64_t* out, int logN, int L, const PrimeSet& ps,
+                         const TwSet& tws, hipStream_t st);
+hipError_t launch_encrypt(const uint64_t* a, const int16_t* e, const int32_t* msgs,
+                          const uint64_t* sk_ntt, uint64_t* ct, int Qd, int L, int logN,
+                          uint32_t t, const PrimeSet& ps, const TwSet& tws, hipStream_t st);
+hipError_t launch_decrypt(const uint64_t* ct, int M, const uint64_t* sk_ntt,
+                          const uint32_t* qnorm2, uint32_t* out, int L, int logN,
+                          const PrimeSet& ps, const TwSet& tws, const DecodeConst& D,
+                          hipStream_t st);
+hipError_t launch_mult_plain(const uint64_t* cq, const uint2* db, int i, int k, int d, int C,
+                             int L, int logN, const PrimeSet& ps, uint64_t* tmp,
+                             hipStream_t st);
+hipError_t launch_add(uint64_t* acc, const uint64_t* tmp, int L, int logN, const PrimeSet& ps,
+                      hipStream_t st);
+hipError_t launch_add_plain(uint64_t* ct, const uint32_t* share, const uint32_t* norms, int k,
+                            int L, int logN, uint32_t t, const PrimeSet& ps, hipStream_t st);
+
+}  // namespace sanns

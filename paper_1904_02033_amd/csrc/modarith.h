@@ -1,0 +1,108 @@
+// Device modular arithmetic for residues below 2^54, built from the 32-bit
+// multiplier (v_mul_hi_u32, v_mul_lo_u32, v_mad_u64_u32 all issue at full
+// rate on gfx950, so every wide product below is spelled out in 32-bit
+// pieces).
+//
+// Shoup multiplication by a fixed operand w < q with companion
+// w' = floor(w * 2^64 / q):  for any x < 2^64,
+//     Qhat = floor(x w' / 2^64)  and  r = x w - Qhat q  (mod 2^64)
+// satisfy 0 <= r < 2q, because x w / q - Qhat < x / 2^64 + 1 < 2.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sanns {
+
+__device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
+__device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
+
+__device__ __forceinline__ uint64_t mul32x32(uint32_t a, uint32_t b) {
+  return (uint64_t)a * b;
+}
+
+// Exact floor(x * y / 2^64).
+__device__ __forceinline__ uint64_t mulhi64(uint64_t x, uint64_t y) {
+  uint32_t x0 = lo32(x), x1 = hi32(x), y0 = lo32(y), y1 = hi32(y);
+  uint64_t t = mul32x32(x0, y1) + __umulhi(x0, y0);  // < 2^64
+  uint64_t u = mul32x32(x1, y0) + lo32(t);           // < 2^64
+  return mul32x32(x1, y1) + hi32(t) + hi32(u);
+}
+
+// x * y mod 2^64.
+__device__ __forceinline__ uint64_t mullo64(uint64_t x, uint64_t y) {
+  uint32_t x0 = lo32(x), x1 = hi32(x), y0 = lo32(y), y1 = hi32(y);
+  uint64_t p = mul32x32(x0, y0);
+  uint32_t cross = x0 * y1 + x1 * y0;
+  return p + ((uint64_t)cross << 32);
+}
+
+// Shoup product in [0, 2q) for any x < 2^64.
+__device__ __forceinline__ uint64_t shoup_lazy(uint64_t x, uint64_t w, uint64_t wp,
+                                               uint64_t q) {
+  uint64_t Q = mulhi64(x, wp);
+  return mullo64(x, w) - mullo64(Q, q);
+}
+
+__device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t q) {
+  return x >= q ? x - q : x;
+}
+
+// Shoup product reduced to [0, q).
+__device__ __forceinline__ uint64_t shoup(uint64_t x, uint64_t w, uint64_t wp,
+                                          uint64_t q) {
+  return csub(shoup_lazy(x, w, wp, q), q);
+}
+
+// x mod q for any x < 2^64, with one = floor(2^64 / q) (Shoup with w = 1).
+__device__ __forceinline__ uint64_t reduce64(uint64_t x, uint64_t one, uint64_t q) {
+  uint64_t r = x - mullo64(mulhi64(x, one), q);
+  return csub(r, q);
+}
+
+__device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) {
+  return csub(a + b, q);
+}
+__device__ __forceinline__ uint64_t submod(uint64_t a, uint64_t b, uint64_t q) {
+  return a >= b ? a - b : a + q - b;
+}
+
+// Constants of one RNS prime, passed to kernels by value.
+struct Prime {
+  uint64_t q;
+  uint64_t one;      // floor(2^64 / q)
+  uint64_t c54;      // 2^54 mod q
+  uint64_t c54p;     // Shoup companion of c54
+  uint64_t delta;    // floor(Q / t) mod q   (Q the whole modulus)
+  uint64_t deltap;   // Shoup companion of delta
+  uint64_t ninv;     // N^-1 mod q
+  uint64_t ninvp;
+};
+
+// Multiply-accumulate of 54-bit residues in 27-bit halves (Karatsuba):
+// a = a1 2^27 + a0, b = b1 2^27 + b0,
+//   a b = a1 b1 2^54 + ((a0 + a1)(b0 + b1) - a0 b0 - a1 b1) 2^27 + a0 b0.
+// Each product is below 2^56, so up to 255 terms fit the 64-bit sums.
+struct Acc3 {
+  uint64_t lo, mid, hi;
+};
+
+__device__ __forceinline__ void acc3_zero(Acc3 &a) { a.lo = a.mid = a.hi = 0; }
+
+// Fold an accumulator into a residue in [0, q):
+//   V = hi 2^54 + (mid - lo - hi) 2^27 + lo = H 2^54 + W  with
+//   H = hi + (m >> 27), W = (m mod 2^27) 2^27 + lo, both below 2^64.
+__device__ __forceinline__ uint64_t acc3_reduce(const Acc3 &a, const Prime &P) {
+  uint64_t m = a.mid - a.lo - a.hi;
+  uint64_t H = a.hi + (m >> 27);
+  uint64_t W = ((m & ((1ull << 27) - 1)) << 27) + a.lo;
+  uint64_t r = shoup_lazy(H, P.c54, P.c54p, P.q) + shoup_lazy(W, 1, P.one, P.q);
+  r = csub(r, 2 * P.q);
+  return csub(r, P.q);
+}
+
+__device__ __forceinline__ void split27(uint64_t x, uint32_t &x0, uint32_t &x1) {
+  x0 = lo32(x) & ((1u << 27) - 1);
+  x1 = (uint32_t)(x >> 27);
+}
+
+}  // namespace sanns

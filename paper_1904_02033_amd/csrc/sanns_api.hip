@@ -1,0 +1,615 @@
+// C ABI of the homomorphic distance stage (see include/sanns.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sanns.h"
+#include "kernels.h"
+#include "launch.h"
+#include "params.h"
+
+using namespace sanns;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sanns_status fail(sanns_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                             \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return fail(SANNS_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Cache key of a captured batched launch sequence.
+struct GraphKey {
+  const void* db;
+  uint32_t C, d, Q, M;
+  const void* ct_in;
+  const void* qids;
+  const void* ct_out;
+  const void* share;
+  const void* ws;
+  int qt, ct, n_tiles, table;
+  uint32_t key[8];
+  bool operator<(const GraphKey& o) const { return std::memcmp(this, &o, sizeof *this) < 0; }
+};
+
+}  // namespace
+
+struct sanns_ctx {
+  sanns_params p{};
+  int device = 0;
+  int logN = 0;
+  PrimeSet ps{};
+  TwSet tws{};
+  DecodeConst dec{};
+  uint64_t tone = 0;  // floor(2^64 / t)
+  uint64_t* d_tw = nullptr;
+  uint32_t* d_err = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::mutex mu;
+  std::map<GraphKey, hipGraphExec_t> graphs;
+  // pinned staging for host-built schedules
+  void* staging = nullptr;
+  size_t staging_bytes = 0;
+  hipEvent_t staging_done = nullptr;
+  // schedule override (0 = automatic)
+  int force_qt = 0, force_ct = 0;
+};
+
+namespace {
+
+int log2u(uint32_t x) {
+  int l = 0;
+  while ((1u << l) < x) ++l;
+  return l;
+}
+
+const int kLogqCap[] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 27, 54, 109, 218, 438, 881};
+
+sanns_status check_params(const sanns_params* p) {
+  if (!p) return fail(SANNS_E_INVALID, "null parameters");
+  if (p->N < 16 || p->N > 16384 || (p->N & (p->N - 1)))
+    return fail(SANNS_E_INVALID, "N = %u is not a power of two in [16, 16384]", p->N);
+  if (p->L < 1 || p->L > SANNS_MAX_LIMBS)
+    return fail(SANNS_E_INVALID, "L = %u outside [1, %d]", p->L, SANNS_MAX_LIMBS);
+  if (p->t < 2 || p->t >= (1ull << 31))
+    return fail(SANNS_E_PARAMS, "t = %llu outside [2, 2^31)", (unsigned long long)p->t);
+  for (uint32_t l = 0; l < p->L; ++l) {
+    const uint64_t q = p->q[l];
+    if (q <= (1ull << 32) || q >= (1ull << 54))
+      return fail(SANNS_E_PARAMS, "q[%u] outside (2^32, 2^54)", l);
+    if (q % (2ull * p->N) != 1) return fail(SANNS_E_PARAMS, "q[%u] != 1 mod 2N", l);
+    if (!host::is_prime(q)) return fail(SANNS_E_PARAMS, "q[%u] is not prime", l);
+    for (uint32_t j = 0; j < l; ++j)
+      if (p->q[j] == q) return fail(SANNS_E_PARAMS, "q[%u] repeats q[%u]", l, j);
+  }
+  std::vector<uint64_t> qs(p->q, p->q + p->L);
+  const int bits = host::log2q_bits(qs);
+  const int logN = log2u(p->N);
+  if (!(p->flags & SANNS_FLAG_INSECURE_TEST)) {
+    if (logN < 10) return fail(SANNS_E_PARAMS, "N < 1024 needs SANNS_FLAG_INSECURE_TEST");
+    if (bits > kLogqCap[logN])
+      return fail(SANNS_E_PARAMS, "log2 q = %d exceeds the 128-bit cap %d for N = %u", bits,
+                  kLogqCap[logN], p->N);
+  }
+  return SANNS_OK;
+}
+
+// Choose the (queries x chunks) register tile of the multiply-accumulate.
+void choose_shape(const sanns_ctx* ctx, uint32_t Q, int& qt, int& ct) {
+  if (ctx->force_qt > 0) {
+    qt = ctx->force_qt;
+    ct = ctx->force_ct;
+    return;
+  }
+  if (Q <= 1) {
+    qt = 1;
+    ct = 4;
+  } else {
+    qt = 2;
+    ct = 4;
+  }
+}
+
+// Host-built schedule for an explicit work list: group the outputs by chunk,
+// split each chunk's queries into groups of qt, and pack chunks that share a
+// query group ct at a time.
+std::vector<int32_t> build_tiles(const uint32_t* work, uint32_t M, int qt, int ct,
+                                 int* n_tiles) {
+  std::map<uint32_t, std::vector<std::pair<uint32_t, uint32_t>>> by_chunk;  // k -> (q, m)
+  for (uint32_t m = 0; m < M; ++m) by_chunk[work[2 * m + 1]].push_back({work[2 * m], m});
+  std::map<std::vector<uint32_t>, std::vector<std::pair<uint32_t, std::vector<int32_t>>>>
+      groups;  // query group -> (chunk, outs)
+  for (auto& kv : by_chunk) {
+    auto& v = kv.second;
+    std::sort(v.begin(), v.end());
+    for (size_t s = 0; s < v.size(); s += qt) {
+      std::vector<uint32_t> g;
+      std::vector<int32_t> outs;
+      for (size_t a = s; a < std::min(v.size(), s + qt); ++a) {
+        g.push_back(v[a].first);
+        outs.push_back((int32_t)v[a].second);
+      }
+      groups[g].push_back({kv.first, outs});
+    }
+  }
+  const int words = qt + ct + qt * ct;
+  std::vector<int32_t> out;
+  int nt = 0;
+  for (auto& kv : groups) {
+    const auto& g = kv.first;
+    const auto& lst = kv.second;
+    for (size_t s = 0; s < lst.size(); s += ct) {
+      std::vector<int32_t> T(words, -1);
+      for (int a = 0; a < qt; ++a) T[a] = (int32_t)(a < (int)g.size() ? g[a] : g[0]);
+      for (int b = 0; b < ct; ++b) {
+        const size_t e = s + b;
+        T[qt + b] = (int32_t)(e < lst.size() ? lst[e].first : lst[s].first);
+        for (int a = 0; a < qt; ++a)
+          T[qt + ct + a * ct + b] =
+              (e < lst.size() && a < (int)g.size()) ? lst[e].second[a] : -1;
+      }
+      out.insert(out.end(), T.begin(), T.end());
+      ++nt;
+    }
+  }
+  *n_tiles = nt;
+  return out;
+}
+
+// Copy host bytes to device memory on `st` through the context's pinned
+// staging buffer (the previous copy out of it is awaited first).
+sanns_status stage_upload(sanns_ctx* ctx, void* dst, const void* src, size_t bytes,
+                          hipStream_t st) {
+  if (!bytes) return SANNS_OK;
+  HIP_TRY(hipEventSynchronize(ctx->staging_done));
+  if (bytes > ctx->staging_bytes) {
+    if (ctx->staging) HIP_TRY(hipHostFree(ctx->staging));
+    ctx->staging = nullptr;
+    ctx->staging_bytes = 0;
+    HIP_TRY(hipHostMalloc(&ctx->staging, bytes, hipHostMallocDefault));
+    ctx->staging_bytes = bytes;
+  }
+  std::memcpy(ctx->staging, src, bytes);
+  HIP_TRY(hipMemcpyAsync(dst, ctx->staging, bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(ctx->staging_done, st));
+  return SANNS_OK;
+}
+
+struct WsLayout {
+  size_t qntt, tiles, work, tmp, total;
+};
+
+WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M) {
+  const size_t N = ctx->p.N, L = ctx->p.L;
+  WsLayout w;
+  size_t off = 0;
+  w.qntt = off;
+  off += align256((size_t)Q * d * 2 * L * N * 8);
+  w.tiles = off;
+  off += align256((size_t)M * 64 * sizeof(int32_t));  // >= M tiles of the largest shape
+  w.work = off;
+  off += align256((size_t)M * 2 * sizeof(uint32_t));
+  w.tmp = off;
+  off += align256(2 * L * N * 8);
+  w.total = off;
+  return w;
+}
+
+}  // namespace
+
+// ===========================================================================
+// context
+// ===========================================================================
+
+extern "C" const char* sanns_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" sanns_status sanns_params_derive(uint32_t N, uint32_t L, uint32_t t_bits,
+                                           sanns_params* out) {
+  if (!out) return fail(SANNS_E_INVALID, "null output");
+  if (N < 16 || N > 16384 || (N & (N - 1)))
+    return fail(SANNS_E_INVALID, "N = %u is not a power of two in [16, 16384]", N);
+  if (L < 1 || L > SANNS_MAX_LIMBS) return fail(SANNS_E_INVALID, "L = %u outside [1, 4]", L);
+  if (t_bits < 2 || t_bits > 31) return fail(SANNS_E_INVALID, "t_bits outside [2, 31]");
+  std::memset(out, 0, sizeof *out);
+  out->N = N;
+  out->L = L;
+  const auto qs = host::rns_primes(N, L);
+  if (qs.size() != L) return fail(SANNS_E_PARAMS, "not enough primes");
+  for (uint32_t l = 0; l < L; ++l) out->q[l] = qs[l];
+  out->t = host::plain_modulus(N, t_bits);
+  out->flags = 0;
+  return SANNS_OK;
+}
+
+extern "C" sanns_status sanns_ctx_create(const sanns_params* p, int device, sanns_ctx** out) {
+  if (!out) return fail(SANNS_E_INVALID, "null output");
+  *out = nullptr;
+  sanns_status s = check_params(p);
+  if (s != SANNS_OK) return s;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev)
+    return fail(SANNS_E_INVALID, "device %d outside [0, %d)", device, ndev);
+  HIP_TRY(hipSetDevice(device));
+  sanns_ctx* ctx = new sanns_ctx();
+  ctx->p = *p;
+  ctx->device = device;
+  ctx->logN = log2u(p->N);
+  const uint32_t N = p->N, L = p->L;
+  std::vector<uint64_t> qs(p->q, p->q + L);
+  const auto deltas = host::delta_mod_limbs(qs, p->t);
+  std::vector<uint64_t> tw_all;
+  try {
+    for (uint32_t l = 0; l < L; ++l) {
+      ctx->ps.p[l] = host::prime_consts(N, qs[l], deltas[l]);
+      const uint64_t psi = host::min_primitive_root_2n(N, qs[l]);
+      const auto tw = host::twiddle_table(N, qs[l], psi);
+      tw_all.insert(tw_all.end(), tw.begin(), tw.end());
+    }
+    ctx->dec = host::decode_consts(qs, p->t);
+  } catch (const std::exception& e) {
+    delete ctx;
+    return fail(SANNS_E_PARAMS, "%s", e.what());
+  }
+  ctx->tone = (uint64_t)((((unsigned __int128)1) << 64) / p->t);
+  hipError_t e = hipMalloc(&ctx->d_tw, tw_all.size() * sizeof(uint64_t));
+  if (e != hipSuccess) {
+    delete ctx;
+    return fail(SANNS_E_NOMEM, "twiddle tables: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpy(ctx->d_tw, tw_all.data(), tw_all.size() * sizeof(uint64_t),
+                hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&ctx->d_err, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipMemset(ctx->d_err, 0, sizeof(uint32_t));
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ctx->staging_done, ctx->cap_stream);
+  if (e != hipSuccess) {
+    sanns_ctx_destroy(ctx);
+    return fail(SANNS_E_DEVICE, "context setup: %s", hipGetErrorString(e));
+  }
+  for (uint32_t l = 0; l < L; ++l) ctx->tws.tw[l] = ctx->d_tw + (size_t)l * 4 * N;
+  *out = ctx;
+  return SANNS_OK;
+}
+
+extern "C" void sanns_ctx_destroy(sanns_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (ctx->staging_done) (void)hipEventSynchronize(ctx->staging_done);
+  if (ctx->staging) (void)hipHostFree(ctx->staging);
+  if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->d_tw) (void)hipFree(ctx->d_tw);
+  if (ctx->d_err) (void)hipFree(ctx->d_err);
+  delete ctx;
+}
+
+extern "C" sanns_status sanns_ctx_params(const sanns_ctx* ctx, sanns_params* out) {
+  if (!ctx || !out) return fail(SANNS_E_INVALID, "null argument");
+  *out = ctx->p;
+  return SANNS_OK;
+}
+
+extern "C" sanns_status sanns_device_status(sanns_ctx* ctx, void* stream) {
+  if (!ctx) return fail(SANNS_E_INVALID, "null context");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  uint32_t v = 0;
+  HIP_TRY(hipMemcpy(&v, ctx->d_err, sizeof v, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(ctx->d_err, 0, sizeof v));
+  if (v & 1u) return fail(SANNS_E_RANGE, "an input residue was >= its prime");
+  if (v & 2u) return fail(SANNS_E_RANGE, "a slot index was outside [-1, n)");
+  return SANNS_OK;
+}
+
+extern "C" sanns_status sanns_set_schedule(sanns_ctx* ctx, int qt, int ct) {
+  if (!ctx) return fail(SANNS_E_INVALID, "null context");
+  if (qt == 0 && ct == 0) {
+    ctx->force_qt = ctx->force_ct = 0;
+    return SANNS_OK;
+  }
+  if (mac_tile_bytes(qt, ct) == 0)
+    return fail(SANNS_E_INVALID, "tile %dx%d is not built", qt, ct);
+  ctx->force_qt = qt;
+  ctx->force_ct = ct;
+  return SANNS_OK;
+}
+
+// ===========================================================================
+// database
+// ===========================================================================
+
+extern "C" size_t sanns_db_bytes(const sanns_ctx* ctx, uint32_t n_chunks, uint32_t d) {
+  if (!ctx) return 0;
+  const size_t N = ctx->p.N, L = ctx->p.L;
+  return L * n_chunks * d * N * 8 + (size_t)n_chunks * N * 4;
+}
+
+extern "C" sanns_status sanns_encode_db(sanns_ctx* ctx, const void* points, int dtype,
+                                        uint64_t n, const int64_t* slot_point,
+                                        const sanns_db* db, void* stream) {
+  if (!ctx || !points || !slot_point || !db || !db->mem)
+    return fail(SANNS_E_INVALID, "null argument");
+  if (dtype != SANNS_U8 && dtype != SANNS_I8) return fail(SANNS_E_INVALID, "bad dtype");
+  if (db->d == 0 || db->d > SANNS_MAX_D || db->n_chunks == 0 || n == 0)
+    return fail(SANNS_E_INVALID, "bad database shape (n=%llu, d=%u, chunks=%u)",
+                (unsigned long long)n, db->d, db->n_chunks);
+  if (db->bytes < sanns_db_bytes(ctx, db->n_chunks, db->d))
+    return fail(SANNS_E_WORKSPACE, "database buffer too small");
+  // every squared distance must stay below t (b_d = 2 b_c + ceil(log2 d))
+  if ((uint64_t)db->d * 255ull * 255ull >= ctx->p.t)
+    return fail(SANNS_E_RANGE, "d * 255^2 = %llu does not fit below t",
+                (unsigned long long)db->d * 65025ull);
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t N = ctx->p.N, L = ctx->p.L, C = db->n_chunks, d = db->d;
+  uint2* res = (uint2*)db->mem;
+  uint32_t* norms = (uint32_t*)((char*)db->mem + (size_t)L * C * d * N * 8);
+  const uint32_t batch = std::max<uint32_t>(1, std::min<uint32_t>(C, (64u << 20) / (d * N * 2)));
+  int16_t* gt = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&gt, (size_t)batch * d * N * sizeof(int16_t), st));
+  for (uint32_t k0 = 0; k0 < C; k0 += batch) {
+    const uint32_t nk = std::min(batch, C - k0);
+    HIP_TRY(launch_gather(points, dtype == SANNS_I8, (long)n, (int)d, slot_point,
+                          (long)k0 * N, (long)nk * N, ctx->logN, gt, norms, ctx->d_err, st));
+    HIP_TRY(launch_encode_ntt(gt, res, (int)k0, (int)nk, (int)C, (int)d, ctx->logN, (int)L,
+                              ctx->ps, ctx->tws, st));
+  }
+  HIP_TRY(hipFreeAsync(gt, st));
+  return SANNS_OK;
+}
+
+// ===========================================================================
+// client helpers
+// ===========================================================================
+
+extern "C" sanns_status sanns_encrypt_query(sanns_ctx* ctx, const int8_t* sk,
+                                            const int32_t* msgs, uint32_t Q, uint32_t d,
+                                            const uint64_t* a, const int16_t* e,
+                                            uint64_t* ct_out, void* stream) {
+  if (!ctx || !sk || !msgs || !a || !e || !ct_out) return fail(SANNS_E_INVALID, "null argument");
+  if (Q == 0 || d == 0 || d > SANNS_MAX_D) return fail(SANNS_E_INVALID, "bad Q or d");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t N = ctx->p.N, L = ctx->p.L;
+  uint64_t* sk_ntt = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&sk_ntt, (size_t)L * N * 8, st));
+  HIP_TRY(launch_sk_ntt(sk, sk_ntt, ctx->logN, (int)L, ctx->ps, ctx->tws, st));
+  HIP_TRY(launch_encrypt(a, e, msgs, sk_ntt, ct_out, (int)(Q * d), (int)L, ctx->logN,
+                         (uint32_t)ctx->p.t, ctx->ps, ctx->tws, st));
+  HIP_TRY(hipFreeAsync(sk_ntt, st));
+  return SANNS_OK;
+}
+
+extern "C" sanns_status sanns_decrypt_shares(sanns_ctx* ctx, const int8_t* sk,
+                                             const uint64_t* ct, uint32_t M,
+                                             const uint32_t* qnorm2, uint32_t* client_share,
+                                             void* stream) {
+  if (!ctx || !sk || !ct || !client_share) return fail(SANNS_E_INVALID, "null argument");
+  if (M == 0) return SANNS_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t N = ctx->p.N, L = ctx->p.L;
+  uint64_t* sk_ntt = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&sk_ntt, (size_t)L * N * 8, st));
+  HIP_TRY(launch_sk_ntt(sk, sk_ntt, ctx->logN, (int)L, ctx->ps, ctx->tws, st));
+  HIP_TRY(launch_decrypt(ct, (int)M, sk_ntt, qnorm2, client_share, (int)L, ctx->logN, ctx->ps,
+                         ctx->tws, ctx->dec, st));
+  HIP_TRY(hipFreeAsync(sk_ntt, st));
+  return SANNS_OK;
+}
+
+// ===========================================================================
+// server hot path
+// ===========================================================================
+
+extern "C" size_t sanns_distances_workspace(const sanns_ctx* ctx, const sanns_db* db,
+                                            uint32_t Q, uint32_t M, int mode) {
+  (void)mode;
+  if (!ctx || !db) return 0;
+  return ws_layout(ctx, db->d, Q, M).total;
+}
+
+namespace {
+
+// The fused sequence: query NTT, masks, multiply-accumulate, INTT + mask.
+sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* ct_in,
+                           uint32_t Q, const MaskKey& K, const uint64_t* qids,
+                           const uint32_t* dwork, uint32_t M, int qt, int ct,
+                           const void* dtiles, int n_tiles, uint64_t* ct_out,
+                           uint32_t* share, uint64_t* qntt, hipStream_t st) {
+  const uint32_t N = ctx->p.N, L = ctx->p.L, C = db->n_chunks, d = db->d;
+  const uint2* res = (const uint2*)db->mem;
+  const uint32_t* norms = (const uint32_t*)((const char*)db->mem + (size_t)L * C * d * N * 8);
+  HIP_TRY(launch_ntt_fwd(ct_in, qntt, (int)(Q * d * 2 * L), ctx->logN, (int)L, ctx->ps,
+                         ctx->tws, ctx->d_err, st));
+  HIP_TRY(launch_masks(K, qids, dwork, (int)C, (int)M, ctx->logN, (uint32_t)ctx->p.t, ctx->tone,
+                       share, st));
+  HIP_TRY(launch_mac(qt, ct, qntt, res, dtiles, n_tiles, (int)Q, (int)d, (int)L, ctx->logN,
+                     (int)C, ctx->ps, ct_out, st));
+  HIP_TRY(launch_intt_mask(ct_out, share, norms, dwork, (int)C, (int)M, ctx->logN, (int)L,
+                           (uint32_t)ctx->p.t, ctx->ps, ctx->tws, st));
+  return SANNS_OK;
+}
+
+// One launch per ciphertext operation, in the order a BFV library would issue
+// them: NTT(c_i); per chunk: multiply_plain + add over i, INTT, sample mask,
+// add_plain.
+sanns_status enqueue_plain(sanns_ctx* ctx, const sanns_db* db, const uint64_t* ct_in,
+                           uint32_t Q, const MaskKey& K, const uint64_t* qids,
+                           const std::vector<uint32_t>& hwork, const uint32_t* dwork,
+                           uint32_t M, uint64_t* ct_out, uint32_t* share, uint64_t* qntt,
+                           uint64_t* tmp, hipStream_t st) {
+  const uint32_t N = ctx->p.N, L = ctx->p.L, C = db->n_chunks, d = db->d;
+  const uint2* res = (const uint2*)db->mem;
+  const uint32_t* norms = (const uint32_t*)((const char*)db->mem + (size_t)L * C * d * N * 8);
+  const size_t ctw = (size_t)2 * L * N;
+  for (uint32_t qi = 0; qi < Q; ++qi)
+    for (uint32_t i = 0; i < d; ++i)
+      HIP_TRY(launch_ntt_fwd(ct_in + ((size_t)qi * d + i) * ctw, qntt + ((size_t)qi * d + i) * ctw,
+                             (int)(2 * L), ctx->logN, (int)L, ctx->ps, ctx->tws, ctx->d_err, st));
+  for (uint32_t m = 0; m < M; ++m) {
+    const uint32_t qi = hwork[2 * m], k = hwork[2 * m + 1];
+    uint64_t* acc = ct_out + (size_t)m * ctw;
+    for (uint32_t i = 0; i < d; ++i) {
+      const uint64_t* cq = qntt + ((size_t)qi * d + i) * ctw;
+      if (i == 0) {
+        HIP_TRY(launch_mult_plain(cq, res, (int)i, (int)k, (int)d, (int)C, (int)L, ctx->logN,
+                                  ctx->ps, acc, st));
+      } else {
+        HIP_TRY(launch_mult_plain(cq, res, (int)i, (int)k, (int)d, (int)C, (int)L, ctx->logN,
+                                  ctx->ps, tmp, st));
+        HIP_TRY(launch_add(acc, tmp, (int)L, ctx->logN, ctx->ps, st));
+      }
+    }
+    HIP_TRY(launch_ntt_inv(acc, (int)(2 * L), ctx->logN, (int)L, ctx->ps, ctx->tws, st));
+    HIP_TRY(launch_masks(K, qids, dwork + 2 * m, (int)C, 1, ctx->logN, (uint32_t)ctx->p.t,
+                         ctx->tone, share + (size_t)m * N, st));
+    HIP_TRY(launch_add_plain(acc, share + (size_t)m * N, norms, (int)k, (int)L, ctx->logN,
+                             (uint32_t)ctx->p.t, ctx->ps, st));
+  }
+  return SANNS_OK;
+}
+
+}  // namespace
+
+extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
+                                        const uint64_t* ct_in, uint32_t Q,
+                                        const uint8_t* mask_key, const uint64_t* query_ids,
+                                        const uint32_t* work, uint32_t M, int mode,
+                                        uint64_t* ct_out, uint32_t* server_share,
+                                        void* workspace, size_t ws_bytes, void* stream) {
+  if (!ctx || !db || !db->mem || !ct_in || !mask_key || !query_ids || !ct_out ||
+      !server_share || !workspace)
+    return fail(SANNS_E_INVALID, "null argument");
+  if (mode != SANNS_MODE_PLAIN && mode != SANNS_MODE_FUSED && mode != SANNS_MODE_BATCHED)
+    return fail(SANNS_E_INVALID, "bad mode %d", mode);
+  if (Q == 0 || db->d == 0 || db->d > SANNS_MAX_D || db->n_chunks == 0)
+    return fail(SANNS_E_INVALID, "bad shape");
+  const uint32_t C = db->n_chunks;
+  if (!work && (uint64_t)M != (uint64_t)Q * C)
+    return fail(SANNS_E_INVALID, "without a work list M must be Q * n_chunks");
+  if (M == 0) return SANNS_OK;
+  if (work)
+    for (uint32_t m = 0; m < M; ++m)
+      if (work[2 * m] >= Q || work[2 * m + 1] >= C)
+        return fail(SANNS_E_RANGE, "work[%u] = (%u, %u) outside Q x n_chunks", m, work[2 * m],
+                    work[2 * m + 1]);
+  const WsLayout W = ws_layout(ctx, db->d, Q, M);
+  if (ws_bytes < W.total)
+    return fail(SANNS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, W.total);
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  uint64_t* qntt = (uint64_t*)(ws + W.qntt);
+  void* dtiles_buf = ws + W.tiles;
+  uint32_t* dwork_buf = (uint32_t*)(ws + W.work);
+  uint64_t* tmp = (uint64_t*)(ws + W.tmp);
+  MaskKey K;
+  for (int i = 0; i < 8; ++i)
+    K.k[i] = (uint32_t)mask_key[4 * i] | (uint32_t)mask_key[4 * i + 1] << 8 |
+             (uint32_t)mask_key[4 * i + 2] << 16 | (uint32_t)mask_key[4 * i + 3] << 24;
+
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (mode == SANNS_MODE_PLAIN) {
+    std::vector<uint32_t> hwork(2 * (size_t)M);
+    if (work)
+      std::memcpy(hwork.data(), work, hwork.size() * sizeof(uint32_t));
+    else
+      for (uint32_t m = 0; m < M; ++m) {
+        hwork[2 * m] = m / C;
+        hwork[2 * m + 1] = m % C;
+      }
+    sanns_status s = stage_upload(ctx, dwork_buf, hwork.data(), hwork.size() * 4, st);
+    if (s != SANNS_OK) return s;
+    return enqueue_plain(ctx, db, ct_in, Q, K, query_ids, hwork, dwork_buf, M, ct_out,
+                         server_share, qntt, tmp, st);
+  }
+
+  int qt, ct;
+  choose_shape(ctx, Q, qt, ct);
+  const void* dtiles = nullptr;
+  const uint32_t* dwork = nullptr;
+  int n_tiles;
+  if (work) {
+    std::vector<int32_t> tiles = build_tiles(work, M, qt, ct, &n_tiles);
+    // tiles and the work list go out in one staged copy
+    std::vector<char> blob(W.work - W.tiles + (size_t)M * 8);
+    std::memcpy(blob.data(), tiles.data(), tiles.size() * 4);
+    std::memcpy(blob.data() + (W.work - W.tiles), work, (size_t)M * 8);
+    sanns_status s = stage_upload(ctx, dtiles_buf, blob.data(), blob.size(), st);
+    if (s != SANNS_OK) return s;
+    dtiles = dtiles_buf;
+    dwork = dwork_buf;
+  } else {
+    n_tiles = (int)(((Q + qt - 1) / qt) * ((C + ct - 1) / ct));
+  }
+
+  if (mode == SANNS_MODE_FUSED)
+    return enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, dtiles, n_tiles,
+                         ct_out, server_share, qntt, st);
+
+  // batched: replay (or capture once) the fused sequence as a hipGraph
+  GraphKey key;
+  std::memset(&key, 0, sizeof key);
+  key.db = db->mem;
+  key.C = C;
+  key.d = db->d;
+  key.Q = Q;
+  key.M = M;
+  key.ct_in = ct_in;
+  key.qids = query_ids;
+  key.ct_out = ct_out;
+  key.share = server_share;
+  key.ws = workspace;
+  key.qt = qt;
+  key.ct = ct;
+  key.n_tiles = n_tiles;
+  key.table = work ? 1 : 0;
+  std::memcpy(key.key, K.k, sizeof K.k);
+  auto it = ctx->graphs.find(key);
+  if (it == ctx->graphs.end()) {
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    sanns_status s = enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, dtiles,
+                                   n_tiles, ct_out, server_share, qntt, ctx->cap_stream);
+    hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (s != SANNS_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return fail(SANNS_E_DEVICE, "capture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(SANNS_E_DEVICE, "instantiate: %s", hipGetErrorString(e));
+    it = ctx->graphs.emplace(key, exec).first;
+  }
+  HIP_TRY(hipGraphLaunch(it->second, st));
+  return SANNS_OK;
+}

@@ -1,0 +1,162 @@
+"""Torch-tensor front end of the C ABI (argument marshalling only).
+
+PyTorch provides device memory and streams; every step of the distance stage
+runs in the HIP kernels of libsanns.so behind ``native``.  Shapes follow
+include/sanns.h.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import native as nat
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+class Context:
+    """A parameter set bound to one device (sanns_ctx)."""
+
+    def __init__(self, N: int = 8192, L: int = 3, t_bits: int = 25, device: int = 0,
+                 params: Optional[nat.sanns_params] = None, insecure: bool = False):
+        p = params if params is not None else nat.sanns_params_derive(N, L, t_bits)
+        if insecure:
+            p.flags |= nat.SANNS_FLAG_INSECURE_TEST
+        self.device = device
+        self.handle = nat.sanns_ctx_create(p, device)
+        self.params = nat.sanns_ctx_params(self.handle)
+        self.N, self.L, self.t = self.params.N, self.params.L, self.params.t
+        self.qs = [self.params.q[l] for l in range(self.L)]
+
+    def close(self):
+        if self.handle:
+            torch.cuda.synchronize(self.device)
+            nat.sanns_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_schedule(self, qt: int, ct: int):
+        nat.sanns_set_schedule(self.handle, qt, ct)
+
+    def device_status(self, stream=None):
+        nat.sanns_device_status(self.handle, _stream(stream))
+
+
+@dataclasses.dataclass
+class Database:
+    mem: torch.Tensor          # uint8 device buffer owning the resident form
+    desc: nat.sanns_db
+    n: int
+    d: int
+    n_chunks: int
+    slot_point: torch.Tensor   # int64 [n_chunks * N] on the device
+
+    @property
+    def nbytes(self) -> int:
+        return self.desc.bytes
+
+
+def linear_slot_map(n: int, N: int, perm: np.ndarray) -> np.ndarray:
+    """Slot s of chunk k holds point perm[kN + s]; padding slots hold -1."""
+    C = (n + N - 1) // N
+    m = np.full(C * N, -1, dtype=np.int64)
+    m[:n] = perm
+    return m
+
+
+def encode_db(ctx: Context, points, slot_point: np.ndarray, stream=None) -> Database:
+    """sanns_encode_db on device copies of ``points`` ([n][d] uint8/int8)
+    and the slot map."""
+    dev = torch.device("cuda", ctx.device)
+    pts = torch.as_tensor(points).to(dev).contiguous()
+    if pts.dtype == torch.uint8:
+        dtype = nat.SANNS_U8
+    elif pts.dtype == torch.int8:
+        dtype = nat.SANNS_I8
+    else:
+        raise ValueError("points must be uint8 or int8")
+    n, d = pts.shape
+    if len(slot_point) % ctx.N:
+        raise ValueError("slot map length must be a multiple of N")
+    C = len(slot_point) // ctx.N
+    sp = torch.as_tensor(np.ascontiguousarray(slot_point, dtype=np.int64)).to(dev)
+    nbytes = nat.sanns_db_bytes(ctx.handle, C, d)
+    mem = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    desc = nat.sanns_db(mem.data_ptr(), nbytes, C, d)
+    nat.sanns_encode_db(ctx.handle, pts.data_ptr(), dtype, n, sp.data_ptr(), desc,
+                        _stream(stream))
+    return Database(mem, desc, n, d, C, sp)
+
+
+def encrypt_query(ctx: Context, sk: torch.Tensor, msgs: torch.Tensor, a: torch.Tensor,
+                  e: torch.Tensor, stream=None) -> torch.Tensor:
+    """Client-side encryption of Q queries: returns ct [Q][d][2][L][N] uint64."""
+    Q, d = msgs.shape
+    ct = torch.empty((Q, d, 2, ctx.L, ctx.N), dtype=torch.uint64, device=msgs.device)
+    nat.sanns_encrypt_query(ctx.handle, _ptr(sk), _ptr(msgs), Q, d, _ptr(a), _ptr(e),
+                            _ptr(ct), _stream(stream))
+    return ct
+
+
+def decrypt_shares(ctx: Context, sk: torch.Tensor, ct: torch.Tensor,
+                   qnorm2: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Client shares [M][N] uint32 of M ciphertexts [M][2][L][N]."""
+    M = ct.shape[0]
+    out = torch.empty((M, ctx.N), dtype=torch.uint32, device=ct.device)
+    nat.sanns_decrypt_shares(ctx.handle, _ptr(sk), _ptr(ct), M, _ptr(qnorm2), _ptr(out),
+                             _stream(stream))
+    return out
+
+
+class Distances:
+    """Output and workspace buffers of sanns_distances for a fixed (Q, M)."""
+
+    def __init__(self, ctx: Context, db: Database, Q: int,
+                 work: Optional[np.ndarray] = None, mode: int = nat.SANNS_MODE_FUSED):
+        self.ctx, self.db, self.Q, self.mode = ctx, db, Q, mode
+        self.work = None if work is None else np.ascontiguousarray(work, dtype=np.uint32)
+        self.M = Q * db.n_chunks if work is None else len(self.work)
+        dev = db.mem.device
+        self.ws_bytes = nat.sanns_distances_workspace(ctx.handle, db.desc, Q, self.M, mode)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.ct_out = torch.empty((self.M, 2, ctx.L, ctx.N), dtype=torch.uint64, device=dev)
+        self.share = torch.empty((self.M, ctx.N), dtype=torch.uint32, device=dev)
+
+    def run(self, ct_in: torch.Tensor, mask_key: bytes, query_ids: torch.Tensor,
+            stream=None):
+        if ct_in.shape[0] != self.Q:
+            raise ValueError("query count differs from the one the buffers were sized for")
+        nat.sanns_distances(self.ctx.handle, self.db.desc, _ptr(ct_in), self.Q, mask_key,
+                            _ptr(query_ids), self.work, self.M, self.mode,
+                            _ptr(self.ct_out), _ptr(self.share), _ptr(self.ws),
+                            self.ws_bytes, _stream(stream))
+        return self.ct_out, self.share
+
+
+def distances(ctx: Context, db: Database, ct_in: torch.Tensor, mask_key: bytes,
+              query_ids: torch.Tensor, work: Optional[np.ndarray] = None,
+              mode: int = nat.SANNS_MODE_FUSED, stream=None):
+    """One-shot sanns_distances: returns (ct_out [M][2][L][N], shares [M][N])."""
+    D = Distances(ctx, db, ct_in.shape[0], work, mode)
+    return D.run(ct_in, mask_key, query_ids, stream)
