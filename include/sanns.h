@@ -242,11 +242,34 @@ sanns_status sanns_distances(sanns_ctx *ctx, const sanns_db *db,
  * encoded as padding). */
 sanns_status sanns_device_status(sanns_ctx *ctx, void *stream);
 
-/* Fix the register tile of the multiply-accumulate kernel to qt queries x
- * ct chunks (the built shapes are 1x1, 1x2, 1x4, 1x8, 2x2, 2x4, 4x2, 2x3,
- * 3x2); qt = ct = 0 restores the automatic choice.  Used by the autotuner.
- * Errors: SANNS_E_INVALID for a shape that is not built. */
-sanns_status sanns_set_schedule(sanns_ctx *ctx, int qt, int ct);
+/* Fix the multiply-accumulate schedule (used by the autotuner):
+ *   lds_variant  LDS-staged kernel used for batches of >= 2 queries against
+ *                every chunk (work == NULL): 1..8, or 0 for the default;
+ *   qt x ct      register tile (queries x chunks per thread) used for every
+ *                other call: 1x1, 1x2, 1x4, 1x8, 2x2, 2x4, 4x2, 2x3, 3x2, or
+ *                0x0 for the automatic choice.
+ * Outputs do not depend on the schedule.  Errors: SANNS_E_INVALID for a
+ * variant or shape that is not built. */
+sanns_status sanns_set_schedule(sanns_ctx *ctx, int lds_variant, int qt, int ct);
+
+/* Phases timed by the profiler, in launch order. */
+#define SANNS_PHASE_QUERY_NTT 0 /* forward NTT of the query ciphertexts     */
+#define SANNS_PHASE_MASKS 1     /* ChaCha20 masks -> server shares          */
+#define SANNS_PHASE_MAC 2       /* multiply-accumulate over the database    */
+#define SANNS_PHASE_INTT_MASK 3 /* INTT + Delta [||p||^2 - r]_t             */
+#define SANNS_N_PHASES 4
+
+/* Per-phase timing of the fused form (tracing aid).  While enabled,
+ * sanns_distances in SANNS_MODE_FUSED or SANNS_MODE_BATCHED records a HIP
+ * event pair around each phase's launch on the caller's stream (batched
+ * calls then launch the kernels directly instead of replaying the graph).
+ * Enabling resets the accumulated times. */
+sanns_status sanns_profile_enable(sanns_ctx *ctx, int on);
+
+/* Synchronise on the recorded events and write, for each phase, the mean
+ * duration in milliseconds over the calls since enabling (ms_out[4], host)
+ * and the number of calls (*calls, host, may be NULL). */
+sanns_status sanns_profile_read(sanns_ctx *ctx, double *ms_out, int *calls);
 
 #ifdef __cplusplus
 }

@@ -287,19 +287,35 @@ k_mac(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db,
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int b = 0; b < CT; ++b) acc3_zero(acc[a][c][b]);
+    // Operands of coordinate i + 1 are loaded while coordinate i is
+    // multiplied; the scheduling barriers keep the compiler from pulling the
+    // split of the new operands (which waits for the loads) above the
+    // multiplies.
+    uint32_t x0[QT][2], x1[QT][2], x01[QT][2];
+    uint2 yv[CT];
+#pragma unroll
+    for (int a = 0; a < QT; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        split27(qb[a][i0 * qstride_i + (size_t)c * L * N], x0[a][c], x1[a][c]);
+        x01[a][c] = x0[a][c] + x1[a][c];
+      }
+#pragma unroll
+    for (int b = 0; b < CT; ++b) yv[b] = dbb[b][i0 * dbstride_i];
     for (int i = i0; i < i1; ++i) {
-      uint32_t x0[QT][2], x1[QT][2], x01[QT][2];
+      const int inext = i + 1 < i1 ? i + 1 : i;
+      uint64_t xn[QT][2];
+      uint2 yn[CT];
 #pragma unroll
       for (int a = 0; a < QT; ++a)
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const uint64_t x = qb[a][i * qstride_i + (size_t)c * L * N];
-          split27(x, x0[a][c], x1[a][c]);
-          x01[a][c] = x0[a][c] + x1[a][c];
-        }
+        for (int c = 0; c < 2; ++c) xn[a][c] = qb[a][inext * qstride_i + (size_t)c * L * N];
+#pragma unroll
+      for (int b = 0; b < CT; ++b) yn[b] = dbb[b][inext * dbstride_i];
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int b = 0; b < CT; ++b) {
-        const uint2 y = dbb[b][i * dbstride_i];
+        const uint2 y = yv[b];
         const uint32_t y01 = y.x + y.y;
 #pragma unroll
         for (int a = 0; a < QT; ++a)
@@ -310,6 +326,16 @@ k_mac(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db,
             acc[a][c][b].mid += mul32x32(x01[a][c], y01);
           }
       }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int a = 0; a < QT; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          split27(xn[a][c], x0[a][c], x1[a][c]);
+          x01[a][c] = x0[a][c] + x1[a][c];
+        }
+#pragma unroll
+      for (int b = 0; b < CT; ++b) yv[b] = yn[b];
     }
 #pragma unroll
     for (int a = 0; a < QT; ++a)
@@ -328,6 +354,160 @@ k_mac(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db,
 #pragma unroll
       for (int c = 0; c < 2; ++c) out[(((size_t)o * 2 + c) * L + l) * N + s] = res[a][c][b];
     }
+}
+
+// LDS-staged multiply-accumulate for the every-query-against-every-chunk
+// schedule of a batch.  A block owns S slots of one limb, a tile of QB = QG QT
+// queries and CB = CG CT chunks; per step of DI coordinates it stages the
+// tile's query residues (split into 27-bit halves) and database residues in
+// LDS, and each thread accumulates its QT x CT register tile for one slot.
+// Blocks are numbered so that every XCD (blocks b with equal b mod 8) walks
+// its own range of (slot tile, limb) pairs, all query/chunk tiles of a pair
+// running back to back, which keeps the pair's operands in that XCD's L2.
+template <int QT, int CT, int QG, int CG, int S, int DI>
+__global__ void __launch_bounds__(S * QG * CG)
+k_mac_lds(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db, int Q, int d, int L,
+          int logN, int C, int n_blocks, PrimeSet ps, uint64_t* __restrict__ out) {
+  constexpr int QB = QT * QG, CB = CT * CG, NT = S * QG * CG;
+  constexpr int FOLD = (255 / DI) * DI;  // coordinates per 64-bit accumulation
+  constexpr int QE = QB * 2 * DI * S, DE = CB * DI * S;  // staged words per step
+  constexpr int NQE = (QE + NT - 1) / NT, NDE = (DE + NT - 1) / NT;
+  __shared__ uint2 sq[2][QE];
+  __shared__ uint2 sd[2][DE];
+  const int N = 1 << logN;
+  const int nqt = (Q + QB - 1) / QB, nct = (C + CB - 1) / CB;
+  // XCD-aware decode of the flat block index
+  const int per_xcd = (n_blocks + 7) >> 3;
+  const int lin = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (lin >= n_blocks) return;
+  const int y = lin % (nqt * nct);
+  const int sl = lin / (nqt * nct);
+  const int l = sl % L, st = sl / L;
+  const int q0 = (y % nqt) * QB, k0 = (y / nqt) * CB;
+  const int s0 = st * S;
+  const Prime& P = ps.p[l];
+  const int tid = threadIdx.x;
+  const int s = tid % S, g = tid / S, gq = g % QG, gc = g / QG;
+
+  // global -> registers for the step starting at coordinate i0
+  uint64_t rq[NQE];
+  uint2 rd[NDE];
+  auto fetch = [&](int i0) {
+#pragma unroll
+    for (int u = 0; u < NQE; ++u) {
+      const int e = tid + u * NT;
+      const int ss = e % S, r = e / S;
+      const int di = r % DI, qc = r / DI;
+      const int c = qc & 1, qq = qc >> 1;
+      const int q = q0 + qq < Q ? q0 + qq : Q - 1;
+      const int i = i0 + di;
+      rq[u] = (e < QE && i < d)
+                  ? qntt[((((size_t)q * d + i) * 2 + c) * L + l) * N + s0 + ss]
+                  : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < NDE; ++u) {
+      const int e = tid + u * NT;
+      const int ss = e % S, r = e / S;
+      const int di = r % DI, cc = r / DI;
+      const int k = k0 + cc < C ? k0 + cc : C - 1;
+      const int i = i0 + di;
+      rd[u] = (e < DE && i < d) ? db[(((size_t)l * C + k) * d + i) * N + s0 + ss]
+                                : make_uint2(0u, 0u);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NQE; ++u) {
+      const int e = tid + u * NT;
+      if (e < QE) {
+        uint2 v;
+        split27(rq[u], v.x, v.y);
+        sq[buf][e] = v;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NDE; ++u) {
+      const int e = tid + u * NT;
+      if (e < DE) sd[buf][e] = rd[u];
+    }
+  };
+
+  uint64_t res[QT][2][CT];
+  Acc3 acc[QT][2][CT];
+#pragma unroll
+  for (int a = 0; a < QT; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < CT; ++b) {
+        res[a][c][b] = 0;
+        acc3_zero(acc[a][c][b]);
+      }
+
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int cur = 0;
+  for (int i0 = 0; i0 < d; i0 += DI) {
+    const bool more = i0 + DI < d;
+    if (more) fetch(i0 + DI);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll 2
+    for (int di = 0; di < DI; ++di) {
+      uint32_t x0[QT][2], x1[QT][2], x01[QT][2];
+#pragma unroll
+      for (int a = 0; a < QT; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const uint2 v = sq[cur][(((gq * QT + a) * 2 + c) * DI + di) * S + s];
+          x0[a][c] = v.x;
+          x1[a][c] = v.y;
+          x01[a][c] = v.x + v.y;
+        }
+#pragma unroll
+      for (int b = 0; b < CT; ++b) {
+        const uint2 yv = sd[cur][((gc * CT + b) * DI + di) * S + s];
+        const uint32_t y01 = yv.x + yv.y;
+#pragma unroll
+        for (int a = 0; a < QT; ++a)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            acc[a][c][b].lo += mul32x32(x0[a][c], yv.x);
+            acc[a][c][b].hi += mul32x32(x1[a][c], yv.y);
+            acc[a][c][b].mid += mul32x32(x01[a][c], y01);
+          }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if ((i0 + DI) % FOLD == 0 || !more) {
+#pragma unroll
+      for (int a = 0; a < QT; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int b = 0; b < CT; ++b) {
+            res[a][c][b] = addmod(res[a][c][b], acc3_reduce(acc[a][c][b], P), P.q);
+            acc3_zero(acc[a][c][b]);
+          }
+    }
+    if (more) stash(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+#pragma unroll
+  for (int a = 0; a < QT; ++a) {
+    const int q = q0 + gq * QT + a;
+    if (q >= Q) continue;
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      const int k = k0 + gc * CT + b;
+      if (k >= C) continue;
+      const size_t o = (size_t)q * C + k;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) out[((o * 2 + c) * L + l) * N + s0 + s] = res[a][c][b];
+    }
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -702,6 +882,46 @@ hipError_t launch_mac(int QT, int CT, const uint64_t* qntt, const uint2* db, con
   SANNS_MAC_SHAPES(SANNS_MAC_CASE)
 #undef SANNS_MAC_CASE
   return hipErrorInvalidValue;
+}
+
+template <int QT, int CT, int QG, int CG, int S, int DI>
+static hipError_t launch_mac_lds_t(const uint64_t* qntt, const uint2* db, int Q, int d, int L,
+                                   int logN, int C, const PrimeSet& ps, uint64_t* out,
+                                   hipStream_t st) {
+  constexpr int QB = QT * QG, CB = CT * CG;
+  const int N = 1 << logN;
+  if (N % S) return hipErrorInvalidValue;
+  const long nb = (long)(N / S) * L * ((Q + QB - 1) / QB) * ((C + CB - 1) / CB);
+  if (nb > 0x7fffffffL) return hipErrorInvalidValue;
+  const int per_xcd = (int)((nb + 7) / 8);
+  hipLaunchKernelGGL((k_mac_lds<QT, CT, QG, CG, S, DI>), dim3(per_xcd * 8), dim3(S * QG * CG), 0,
+                     st, qntt, db, Q, d, L, logN, C, (int)nb, ps, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mac_lds(int variant, const uint64_t* qntt, const uint2* db, int Q, int d, int L,
+                          int logN, int C, const PrimeSet& ps, uint64_t* out, hipStream_t st) {
+  switch (variant) {
+#define SANNS_LDS_CASE(id, qt, ct, qg, cg, s, di) \
+  case id:                                        \
+    return launch_mac_lds_t<qt, ct, qg, cg, s, di>(qntt, db, Q, d, L, logN, C, ps, out, st);
+    SANNS_MAC_LDS_VARIANTS(SANNS_LDS_CASE)
+#undef SANNS_LDS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+int mac_lds_min_n(int variant) {
+  switch (variant) {
+#define SANNS_LDS_S(id, qt, ct, qg, cg, s, di) \
+  case id:                                     \
+    return s;
+    SANNS_MAC_LDS_VARIANTS(SANNS_LDS_S)
+#undef SANNS_LDS_S
+    default:
+      return 0;
+  }
 }
 
 hipError_t launch_gather(const void* pts, int is_signed, long n, int d,

@@ -24,6 +24,22 @@ hipError_t launch_mac(int QT, int CT, const uint64_t* qntt, const uint2* db, con
                       int n_tiles, int Q, int d, int L, int logN, int C, const PrimeSet& ps,
                       uint64_t* out, hipStream_t st);
 size_t mac_tile_bytes(int QT, int CT);  // 0 for a shape that is not built
+
+// LDS-staged variants of the all-pairs multiply-accumulate:
+// X(id, QT, CT, QG, CG, S, DI), block = S slots x QG x CG threads covering
+// QG QT queries x CG CT chunks.
+#define SANNS_MAC_LDS_VARIANTS(X)      \
+  X(1, 2, 4, 4, 4, 32, 4)              \
+  X(2, 2, 4, 2, 4, 32, 4)              \
+  X(3, 2, 4, 4, 2, 32, 4)              \
+  X(4, 2, 3, 4, 4, 32, 4)              \
+  X(5, 2, 4, 4, 4, 16, 8)              \
+  X(6, 2, 2, 4, 4, 32, 4)              \
+  X(7, 2, 2, 4, 4, 32, 8)              \
+  X(8, 1, 4, 8, 4, 32, 4)
+hipError_t launch_mac_lds(int variant, const uint64_t* qntt, const uint2* db, int Q, int d, int L,
+                          int logN, int C, const PrimeSet& ps, uint64_t* out, hipStream_t st);
+int mac_lds_min_n(int variant);  // slots per block (N must be a multiple); 0 if unknown
 hipError_t launch_gather(const void* pts, int is_signed, long n, int d,
                          const int64_t* slot_point, long base, long total, int logN,
                          int16_t* gt, uint32_t* norms, uint32_t* err, hipStream_t st);

@@ -50,7 +50,7 @@ struct GraphKey {
   const void* ct_out;
   const void* share;
   const void* ws;
-  int qt, ct, n_tiles, table;
+  int qt, ct, lds, n_tiles, table;
   uint32_t key[8];
   bool operator<(const GraphKey& o) const { return std::memcmp(this, &o, sizeof *this) < 0; }
 };
@@ -75,8 +75,15 @@ struct sanns_ctx {
   size_t staging_bytes = 0;
   hipEvent_t staging_done = nullptr;
   // schedule override (0 = automatic)
-  int force_qt = 0, force_ct = 0;
+  int force_qt = 0, force_ct = 0, force_lds = 0;
+  // per-phase profiling: one event pair per phase and call
+  bool profiling = false;
+  std::vector<std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof_events;
 };
+
+namespace {
+void drop_profile_events(sanns_ctx* ctx);
+}
 
 namespace {
 
@@ -85,6 +92,8 @@ int log2u(uint32_t x) {
   while ((1u << l) < x) ++l;
   return l;
 }
+
+const int kDefaultLdsVariant = 1;  // fastest at 1M x 128, 64 queries
 
 const int kLogqCap[] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 27, 54, 109, 218, 438, 881};
 
@@ -117,14 +126,19 @@ sanns_status check_params(const sanns_params* p) {
   return SANNS_OK;
 }
 
-// Choose the (queries x chunks) register tile of the multiply-accumulate.
-void choose_shape(const sanns_ctx* ctx, uint32_t Q, int& qt, int& ct) {
+// Choose the multiply-accumulate kernel: an LDS-staged variant (lds > 0)
+// for a batch of at least two queries against every chunk, otherwise the
+// (queries x chunks) register tile qt x ct.
+void choose_shape(const sanns_ctx* ctx, uint32_t Q, bool regular, int& qt, int& ct, int& lds) {
+  lds = 0;
+  if (regular && Q >= 2) {
+    lds = ctx->force_lds > 0 ? ctx->force_lds : kDefaultLdsVariant;
+    if ((int)ctx->p.N % mac_lds_min_n(lds) != 0) lds = 0;
+  }
   if (ctx->force_qt > 0) {
     qt = ctx->force_qt;
     ct = ctx->force_ct;
-    return;
-  }
-  if (Q <= 1) {
+  } else if (Q <= 1) {
     qt = 1;
     ct = 4;
   } else {
@@ -300,6 +314,7 @@ extern "C" void sanns_ctx_destroy(sanns_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  drop_profile_events(ctx);
   if (ctx->staging_done) (void)hipEventSynchronize(ctx->staging_done);
   if (ctx->staging) (void)hipHostFree(ctx->staging);
   if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
@@ -327,14 +342,51 @@ extern "C" sanns_status sanns_device_status(sanns_ctx* ctx, void* stream) {
   return SANNS_OK;
 }
 
-extern "C" sanns_status sanns_set_schedule(sanns_ctx* ctx, int qt, int ct) {
+namespace {
+void drop_profile_events(sanns_ctx* ctx) {
+  for (auto& call : ctx->prof_events)
+    for (auto& e : call) {
+      (void)hipEventSynchronize(e.second);
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+  ctx->prof_events.clear();
+}
+}  // namespace
+
+extern "C" sanns_status sanns_profile_enable(sanns_ctx* ctx, int on) {
   if (!ctx) return fail(SANNS_E_INVALID, "null context");
-  if (qt == 0 && ct == 0) {
-    ctx->force_qt = ctx->force_ct = 0;
-    return SANNS_OK;
-  }
-  if (mac_tile_bytes(qt, ct) == 0)
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  drop_profile_events(ctx);
+  ctx->profiling = on != 0;
+  return SANNS_OK;
+}
+
+extern "C" sanns_status sanns_profile_read(sanns_ctx* ctx, double* ms_out, int* calls) {
+  if (!ctx || !ms_out) return fail(SANNS_E_INVALID, "null argument");
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  double sum[SANNS_N_PHASES] = {0, 0, 0, 0};
+  for (auto& call : ctx->prof_events)
+    for (int p = 0; p < SANNS_N_PHASES; ++p) {
+      HIP_TRY(hipEventSynchronize(call[p].second));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, call[p].first, call[p].second));
+      sum[p] += ms;
+    }
+  const int n = (int)ctx->prof_events.size();
+  for (int p = 0; p < SANNS_N_PHASES; ++p) ms_out[p] = n ? sum[p] / n : 0.0;
+  if (calls) *calls = n;
+  return SANNS_OK;
+}
+
+extern "C" sanns_status sanns_set_schedule(sanns_ctx* ctx, int lds_variant, int qt, int ct) {
+  if (!ctx) return fail(SANNS_E_INVALID, "null context");
+  if (lds_variant < 0 || (lds_variant > 0 && mac_lds_min_n(lds_variant) == 0))
+    return fail(SANNS_E_INVALID, "LDS variant %d is not built", lds_variant);
+  if (!(qt == 0 && ct == 0) && mac_tile_bytes(qt, ct) == 0)
     return fail(SANNS_E_INVALID, "tile %dx%d is not built", qt, ct);
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  ctx->force_lds = lds_variant;
   ctx->force_qt = qt;
   ctx->force_ct = ct;
   return SANNS_OK;
@@ -440,20 +492,46 @@ namespace {
 // The fused sequence: query NTT, masks, multiply-accumulate, INTT + mask.
 sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* ct_in,
                            uint32_t Q, const MaskKey& K, const uint64_t* qids,
-                           const uint32_t* dwork, uint32_t M, int qt, int ct,
+                           const uint32_t* dwork, uint32_t M, int qt, int ct, int lds,
                            const void* dtiles, int n_tiles, uint64_t* ct_out,
-                           uint32_t* share, uint64_t* qntt, hipStream_t st) {
+                           uint32_t* share, uint64_t* qntt, hipStream_t st,
+                           bool profile = false) {
   const uint32_t N = ctx->p.N, L = ctx->p.L, C = db->n_chunks, d = db->d;
   const uint2* res = (const uint2*)db->mem;
   const uint32_t* norms = (const uint32_t*)((const char*)db->mem + (size_t)L * C * d * N * 8);
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  if (profile) {
+    ev.resize(SANNS_N_PHASES);
+    for (auto& e : ev) {
+      HIP_TRY(hipEventCreate(&e.first));
+      HIP_TRY(hipEventCreate(&e.second));
+    }
+  }
+  auto mark = [&](int phase, bool end) -> hipError_t {
+    if (!profile) return hipSuccess;
+    return hipEventRecord(end ? ev[phase].second : ev[phase].first, st);
+  };
+  HIP_TRY(mark(SANNS_PHASE_QUERY_NTT, false));
   HIP_TRY(launch_ntt_fwd(ct_in, qntt, (int)(Q * d * 2 * L), ctx->logN, (int)L, ctx->ps,
                          ctx->tws, ctx->d_err, st));
+  HIP_TRY(mark(SANNS_PHASE_QUERY_NTT, true));
+  HIP_TRY(mark(SANNS_PHASE_MASKS, false));
   HIP_TRY(launch_masks(K, qids, dwork, (int)C, (int)M, ctx->logN, (uint32_t)ctx->p.t, ctx->tone,
                        share, st));
-  HIP_TRY(launch_mac(qt, ct, qntt, res, dtiles, n_tiles, (int)Q, (int)d, (int)L, ctx->logN,
-                     (int)C, ctx->ps, ct_out, st));
+  HIP_TRY(mark(SANNS_PHASE_MASKS, true));
+  HIP_TRY(mark(SANNS_PHASE_MAC, false));
+  if (lds > 0)
+    HIP_TRY(launch_mac_lds(lds, qntt, res, (int)Q, (int)d, (int)L, ctx->logN, (int)C, ctx->ps,
+                           ct_out, st));
+  else
+    HIP_TRY(launch_mac(qt, ct, qntt, res, dtiles, n_tiles, (int)Q, (int)d, (int)L, ctx->logN,
+                       (int)C, ctx->ps, ct_out, st));
+  HIP_TRY(mark(SANNS_PHASE_MAC, true));
+  HIP_TRY(mark(SANNS_PHASE_INTT_MASK, false));
   HIP_TRY(launch_intt_mask(ct_out, share, norms, dwork, (int)C, (int)M, ctx->logN, (int)L,
                            (uint32_t)ctx->p.t, ctx->ps, ctx->tws, st));
+  HIP_TRY(mark(SANNS_PHASE_INTT_MASK, true));
+  if (profile) ctx->prof_events.push_back(ev);
   return SANNS_OK;
 }
 
@@ -551,8 +629,8 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
                          server_share, qntt, tmp, st);
   }
 
-  int qt, ct;
-  choose_shape(ctx, Q, qt, ct);
+  int qt, ct, lds;
+  choose_shape(ctx, Q, work == nullptr, qt, ct, lds);
   const void* dtiles = nullptr;
   const uint32_t* dwork = nullptr;
   int n_tiles;
@@ -570,9 +648,9 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
     n_tiles = (int)(((Q + qt - 1) / qt) * ((C + ct - 1) / ct));
   }
 
-  if (mode == SANNS_MODE_FUSED)
-    return enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, dtiles, n_tiles,
-                         ct_out, server_share, qntt, st);
+  if (mode == SANNS_MODE_FUSED || ctx->profiling)
+    return enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, lds, dtiles,
+                         n_tiles, ct_out, server_share, qntt, st, ctx->profiling);
 
   // batched: replay (or capture once) the fused sequence as a hipGraph
   GraphKey key;
@@ -589,6 +667,7 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
   key.ws = workspace;
   key.qt = qt;
   key.ct = ct;
+  key.lds = lds;
   key.n_tiles = n_tiles;
   key.table = work ? 1 : 0;
   std::memcpy(key.key, K.k, sizeof K.k);
@@ -596,8 +675,9 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
   if (it == ctx->graphs.end()) {
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-    sanns_status s = enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, dtiles,
-                                   n_tiles, ct_out, server_share, qntt, ctx->cap_stream);
+    sanns_status s = enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, lds,
+                                   dtiles, n_tiles, ct_out, server_share, qntt,
+                                   ctx->cap_stream);
     hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
     if (s != SANNS_OK) {
       if (graph) (void)hipGraphDestroy(graph);

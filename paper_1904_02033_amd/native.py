@@ -37,7 +37,10 @@ EXPORTS = [
     "sanns_last_error", "sanns_ctx_params", "sanns_db_bytes", "sanns_encode_db",
     "sanns_encrypt_query", "sanns_decrypt_shares", "sanns_distances_workspace",
     "sanns_distances", "sanns_device_status", "sanns_set_schedule",
+    "sanns_profile_enable", "sanns_profile_read",
 ]
+SANNS_N_PHASES = 4
+PHASES = ["query_ntt", "masks", "mac", "intt_mask"]
 
 
 class SannsError(RuntimeError):
@@ -96,8 +99,13 @@ def load() -> ctypes.CDLL:
     L.sanns_distances.restype = st
     L.sanns_device_status.argtypes = [vp, vp]
     L.sanns_device_status.restype = st
-    L.sanns_set_schedule.argtypes = [vp, i32, i32]
+    L.sanns_set_schedule.argtypes = [vp, i32, i32, i32]
     L.sanns_set_schedule.restype = st
+    L.sanns_profile_enable.argtypes = [vp, i32]
+    L.sanns_profile_enable.restype = st
+    L.sanns_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int)]
+    L.sanns_profile_read.restype = st
     _lib = L
     return L
 
@@ -174,5 +182,17 @@ def sanns_device_status(ctx: int, stream: int = 0) -> None:
     _check(load().sanns_device_status(ctx, stream))
 
 
-def sanns_set_schedule(ctx: int, qt: int, ct: int) -> None:
-    _check(load().sanns_set_schedule(ctx, qt, ct))
+def sanns_set_schedule(ctx: int, lds_variant: int, qt: int, ct: int) -> None:
+    _check(load().sanns_set_schedule(ctx, lds_variant, qt, ct))
+
+
+def sanns_profile_enable(ctx: int, on: bool) -> None:
+    _check(load().sanns_profile_enable(ctx, 1 if on else 0))
+
+
+def sanns_profile_read(ctx: int):
+    """Returns ({phase: mean ms}, calls)."""
+    ms = (ctypes.c_double * SANNS_N_PHASES)()
+    calls = ctypes.c_int(0)
+    _check(load().sanns_profile_read(ctx, ms, ctypes.byref(calls)))
+    return dict(zip(PHASES, list(ms))), calls.value

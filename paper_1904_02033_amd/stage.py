@@ -56,8 +56,8 @@ class Context:
         except Exception:
             pass
 
-    def set_schedule(self, qt: int, ct: int):
-        nat.sanns_set_schedule(self.handle, qt, ct)
+    def set_schedule(self, qt: int = 0, ct: int = 0, lds_variant: int = 0):
+        nat.sanns_set_schedule(self.handle, lds_variant, qt, ct)
 
     def device_status(self, stream=None):
         nat.sanns_device_status(self.handle, _stream(stream))

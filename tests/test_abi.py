@@ -84,6 +84,6 @@ def test_host_argument_errors():
         nat.SANNS_E_INVALID
     assert lib.sanns_encrypt_query(None, None, None, 1, 1, None, None, None, None) == \
         nat.SANNS_E_INVALID
-    assert lib.sanns_set_schedule(None, 1, 4) == nat.SANNS_E_INVALID
+    assert lib.sanns_set_schedule(None, 0, 1, 4) == nat.SANNS_E_INVALID
     assert lib.sanns_device_status(None, None) == nat.SANNS_E_INVALID
     lib.sanns_ctx_destroy(None)

@@ -41,10 +41,11 @@ def _dev(x, dtype=None):
 
 
 class GpuRun:
-    def __init__(self, stage, pb, work=None, mode=1, schedule=None):
+    def __init__(self, stage, pb, work=None, mode=1, schedule=None, lds=0):
         self.ctx = _ctx(stage, pb)
-        if schedule:
-            self.ctx.set_schedule(*schedule)
+        if schedule or lds:
+            qt, ct = schedule or (0, 0)
+            self.ctx.set_schedule(qt, ct, lds)
         self.db = stage.encode_db(self.ctx, pb.pts, pb.slot)
         self.sk = _dev(pb.sk)
         self.ct = stage.encrypt_query(self.ctx, self.sk, _dev(pb.queries, torch.int32),
@@ -161,6 +162,23 @@ def test_distances_uneven_work_list(stage, mode, schedule):
     _check_share_sums(pb, work, share, client)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("lds", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("shape", [(256, 2, 25, 256 * 4 + 3, 20, 17, "u8"),
+                                   (256, 2, 26, 300, 300, 3, "i8")])
+def test_lds_mac_variants(stage, lds, mode, shape):
+    """Every LDS-staged variant, with query, chunk and coordinate counts that
+    leave ragged tiles, and with d > 255 (two accumulation folds)."""
+    N, L, tb, n, d, Q, dt = shape
+    pb = make_problem(N, L, tb, n, d, Q, dt, seed=lds + 10 * mode + d)
+    run = GpuRun(stage, pb, mode=mode, lds=lds)
+    out, share, client = run.np()
+    work = _all_work(pb)
+    want_out, want_r = oracle_outputs(pb, work, {})
+    assert (out == want_out).all() and (share == want_r).all()
+    _check_share_sums(pb, work, share, client)
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_workload1_full(stage, mode):
     """Linear scan, 10,000 x 128 uint8, N = 4096, L = 2: every output
@@ -249,6 +267,8 @@ def test_host_errors_with_context(stage):
     assert ei.value.status == nat.SANNS_E_RANGE
     with pytest.raises(nat.SannsError):
         ctx.set_schedule(5, 5)
+    with pytest.raises(nat.SannsError):
+        ctx.set_schedule(lds_variant=99)
     big = make_problem(64, 1, 10, 50, 200, 1, "u8", seed=6)  # d 255^2 >= t
     with pytest.raises(nat.SannsError) as ei:
         stage.encode_db(ctx, big.pts, big.slot)
