@@ -1,0 +1,170 @@
+"""Clustering-based sublinear form of the distance stage (Algorithm 4;
+clustering protocol, steps 5 and 8).
+
+The server keeps two resident databases: the cluster centres (packed and
+randomly permuted, as step 4 shuffles them) and the points, packed cluster by
+cluster followed by the stash (stash points permuted and chunk-aligned).  Per
+query:
+
+  phase 1  HE distances to every centre (a batched linear scan of the centre
+           database);
+  select   the client decrypts and the u closest clusters are chosen in the
+           clear -- a stand-in for the garbled-circuit top-k and the DORAM
+           retrieval of steps 5-6, which are out of scope;
+  phase 2  HE distances to every chunk that holds a point of a selected
+           cluster, plus every stash chunk: an uneven per-query chunk list
+           served by one batched call (the scheduler packs the lists);
+  finish   exact top-k over the selected clusters' points (Algorithm 1),
+           approximate top-k over the stash (Algorithm 2), exact top-k of
+           the 2k candidates (Algorithm 4's last step).
+
+Each resident database has its own mask key, so one query id never draws
+the same mask twice.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import native as nat
+from . import stage, topk
+
+
+@dataclasses.dataclass
+class Layout:
+    slot_point: np.ndarray       # [C N] int64 point index per slot, -1 padding
+    cluster_start: np.ndarray    # [n_clusters] first slot of each cluster
+    cluster_end: np.ndarray      # [n_clusters] one past the last slot
+    stash_start: int             # first stash slot (chunk aligned)
+    stash_end: int
+
+    def chunks_of(self, clusters: Sequence[int], N: int) -> np.ndarray:
+        """Sorted chunks that hold at least one slot of the given clusters."""
+        out = set()
+        for c in clusters:
+            s, e = int(self.cluster_start[c]), int(self.cluster_end[c])
+            if e > s:
+                out.update(range(s // N, (e - 1) // N + 1))
+        return np.array(sorted(out), dtype=np.int64)
+
+    def stash_chunks(self, N: int) -> np.ndarray:
+        return np.arange(self.stash_start // N, (self.stash_end + N - 1) // N,
+                         dtype=np.int64)
+
+
+def pack_clusters(cluster_sizes: np.ndarray, stash_size: int, N: int,
+                  stash_perm: np.ndarray) -> Layout:
+    """Points are stored clusters first (cluster c's points consecutive, in
+    cluster order) then the stash; slots follow the same order, the stash
+    starting on a chunk boundary in the server's random order."""
+    sizes = np.asarray(cluster_sizes, dtype=np.int64)
+    n_clustered = int(sizes.sum())
+    start = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    end = start + sizes
+    stash_start = (n_clustered + N - 1) // N * N
+    total = stash_start + stash_size
+    C = (total + N - 1) // N
+    slot = np.full(C * N, -1, dtype=np.int64)
+    slot[:n_clustered] = np.arange(n_clustered, dtype=np.int64)
+    slot[stash_start:stash_start + stash_size] = n_clustered + np.asarray(stash_perm)
+    return Layout(slot, start, end, stash_start, stash_start + stash_size)
+
+
+class ClusteredServer:
+    """Resident centre and point databases of one clustered index."""
+
+    def __init__(self, ctx: stage.Context, points: np.ndarray, cluster_sizes: np.ndarray,
+                 centers: np.ndarray, stash_size: int, center_perm: np.ndarray,
+                 stash_perm: np.ndarray, key_points: bytes, key_centers: bytes):
+        if key_points == key_centers:
+            raise ValueError("the two resident databases need distinct mask keys")
+        self.ctx = ctx
+        N = ctx.N
+        self.n_clusters = len(cluster_sizes)
+        self.layout = pack_clusters(cluster_sizes, stash_size, N, stash_perm)
+        self.db = stage.encode_db(ctx, points, self.layout.slot_point)
+        self.center_slot = stage.linear_slot_map(self.n_clusters, N, center_perm)
+        self.cdb = stage.encode_db(ctx, centers, self.center_slot)
+        self.key_points, self.key_centers = key_points, key_centers
+        self.n_points = len(points)
+
+    # ---------------------------------------------------------------- phase 1
+    def center_distances(self, ct: torch.Tensor, qids: torch.Tensor,
+                         mode: int = nat.SANNS_MODE_BATCHED, stream=None):
+        """Shares of every query's distances to every centre."""
+        D = stage.Distances(self.ctx, self.cdb, ct.shape[0], mode=mode)
+        return D.run(ct, self.key_centers, qids, stream)
+
+    # ---------------------------------------------------------------- phase 2
+    def work_list(self, selected: Sequence[Sequence[int]]) -> np.ndarray:
+        """(query, chunk) pairs: chunks of each query's selected clusters,
+        then the stash chunks."""
+        N = self.ctx.N
+        stash = self.layout.stash_chunks(N)
+        work = []
+        for q, cl in enumerate(selected):
+            ks = np.union1d(self.layout.chunks_of(cl, N), stash)
+            work += [(q, int(k)) for k in ks]
+        return np.array(work, dtype=np.uint32).reshape(-1, 2)
+
+    def point_distances(self, ct: torch.Tensor, qids: torch.Tensor,
+                        selected: Sequence[Sequence[int]],
+                        mode: int = nat.SANNS_MODE_BATCHED, stream=None):
+        work = self.work_list(selected)
+        D = stage.Distances(self.ctx, self.db, ct.shape[0], work=work, mode=mode)
+        out, share = D.run(ct, self.key_points, qids, stream)
+        return out, share, work
+
+    def requested_pairs(self, selected: Sequence[Sequence[int]]) -> int:
+        """Encrypted distances that phase 2 delivers for requested points."""
+        sz = self.layout.cluster_end - self.layout.cluster_start
+        stash = self.layout.stash_end - self.layout.stash_start
+        return int(sum(int(sz[list(cl)].sum()) + stash for cl in selected))
+
+
+# ---------------------------------------------------------------- client side
+
+def select_clusters(center_dist: np.ndarray, center_slot: np.ndarray, u: int
+                    ) -> np.ndarray:
+    """The u closest clusters from one query's reconstructed centre distances
+    ([C N] in slot order): Algorithm 1 over (distance, cluster id)."""
+    real = center_slot >= 0
+    _, ids = topk.naive_topk(center_dist[real], center_slot[real], u)
+    return ids[ids >= 0]
+
+
+class QueryDistances:
+    """Reconstructed distances of one query from the phase-2 outputs: rows m
+    of (client, server) shares whose work entry names this query."""
+
+    def __init__(self, client: np.ndarray, server: np.ndarray, work: np.ndarray, q: int,
+                 N: int, t: int):
+        rows = np.nonzero(work[:, 0] == q)[0]
+        self.row = np.full(int(work[:, 1].max()) + 1, -1, dtype=np.int64)
+        self.row[work[rows, 1].astype(np.int64)] = rows
+        self.client, self.server, self.N, self.t = client, server, N, t
+
+    def __call__(self, slots: np.ndarray) -> np.ndarray:
+        slots = np.asarray(slots, dtype=np.int64)
+        rows = self.row[slots // self.N]
+        if (rows < 0).any():
+            raise KeyError("a requested slot lies in a chunk this query did not scan")
+        off = slots % self.N
+        return topk.reconstruct(self.client[rows, off], self.server[rows, off], self.t)
+
+
+def finish_query(dist, layout: Layout, selected: Sequence[int], k: int, l_stash: int
+                 ) -> Tuple[np.ndarray, np.ndarray]:
+    """Algorithm 4's selection from reconstructed distances: exact top-k over
+    the selected clusters' points, approximate top-k over the stash, exact
+    top-k of the 2k candidates.  dist(slots) returns the distances of the
+    given slots.  Returns (values, point ids) of the final k."""
+    parts = [np.arange(layout.cluster_start[c], layout.cluster_end[c]) for c in selected]
+    cl_slots = np.concatenate(parts) if parts else np.zeros(0, np.int64)
+    a_v, a_i = topk.naive_topk(dist(cl_slots), layout.slot_point[cl_slots], k)
+    st_slots = np.arange(layout.stash_start, layout.stash_end)
+    b_v, b_i = topk.approx_topk(dist(st_slots), layout.slot_point[st_slots], k, l_stash)
+    return topk.naive_topk(np.concatenate([a_v, b_v]), np.concatenate([a_i, b_i]), k)
