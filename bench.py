@@ -85,41 +85,55 @@ def main():
                     help="comma list of forms to run besides the batched headline")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
+    ap.add_argument("--workload", default="batched-1Mx128",
+                    choices=["batched-1Mx128", "batched-1Mx96", "linear-10Kx128",
+                             "clustered-10M", "serving"])
+    ap.add_argument("--serving-requests", type=int, default=200)
     args = ap.parse_args()
-    forms = set(args.forms.split(","))
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the stage shards by database chunk; see the design notes)", flush=True)
         sys.exit(2)
-
     import torch
     from paper_1904_02033_amd import native as nat
-    from paper_1904_02033_amd import stage
-
     if not os.path.exists(nat.LIB_PATH):
         from paper_1904_02033_amd import build as b
         b.build()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda", 0)
+    if args.workload == "clustered-10M":
+        line = run_clustered(args)
+    elif args.workload == "serving":
+        line = run_serving(args)
+    else:
+        cid = {"batched-1Mx128": 2, "batched-1Mx96": 3, "linear-10Kx128": 1}[args.workload]
+        line = run_linear(args, synthdata.WORKLOADS[cid])
+    print(json.dumps(line), flush=True)
 
-    w = synthdata.WORKLOADS[2]
-    Q = args.queries
+
+def run_linear(args, w):
+    forms = set(args.forms.split(","))
+    import torch
+    from paper_1904_02033_amd import native as nat
+    from paper_1904_02033_amd import stage
+
+    dev = torch.device("cuda", 0)
+    Q = args.queries if w.cid != 1 else 1
     t0 = time.time()
-    pts = synthdata.gen_points(w, n=args.n)
+    pts = synthdata.gen_points(w, n=args.n if w.cid != 1 else w.n)
     queries = synthdata.gen_queries(w, Q)
     n, d = pts.shape
     ctx = stage.Context(w.N, w.L, w.t_bits)
     N, L, t = ctx.N, ctx.L, ctx.t
-    slot = stage.linear_slot_map(n, N, synthdata.gen_perm(n, synthdata.SEED_PERM + 2))
+    slot = stage.linear_slot_map(n, N, synthdata.gen_perm(n, synthdata.SEED_PERM + w.cid))
     db = stage.encode_db(ctx, pts, slot)
     C = db.n_chunks
-    sk = torch.as_tensor(synthdata.gen_secret(N, synthdata.SEED_SK + 2)).to(dev)
-    a = synthdata.gen_uniform_a(ctx.qs, N, Q * d, synthdata.SEED_ENC + 2)
-    e = synthdata.gen_cbd_error(N, Q * d, synthdata.SEED_ENC + 2)
+    sk = torch.as_tensor(synthdata.gen_secret(N, synthdata.SEED_SK + w.cid)).to(dev)
+    a = synthdata.gen_uniform_a(ctx.qs, N, Q * d, synthdata.SEED_ENC + w.cid)
+    e = synthdata.gen_cbd_error(N, Q * d, synthdata.SEED_ENC + w.cid)
     ct = stage.encrypt_query(ctx, sk, torch.as_tensor(queries.astype(np.int32)).to(dev),
                              torch.as_tensor(a).to(dev), torch.as_tensor(e).to(dev))
     del a, e
-    key = synthdata.gen_mask_key(synthdata.SEED_MASK + 2)
+    key = synthdata.gen_mask_key(synthdata.SEED_MASK + w.cid)
     qids = torch.as_tensor(np.arange(Q, dtype=np.uint64)).to(dev)
     torch.cuda.synchronize()
     log(f"setup {time.time() - t0:.1f}s: n={n} d={d} N={N} L={L} C={C} Q={Q}")
@@ -153,8 +167,9 @@ def main():
     tot = (client.cpu().numpy()[0].astype(np.int64) +
            B.share[0].cpu().numpy().astype(np.int64)) % t
     ids = slot[:N]
-    want = ((pts[ids].astype(np.int64) - queries[0].astype(np.int64)) ** 2).sum(axis=1)
-    assert (tot == want).all(), "batched output does not decrypt to the true distances"
+    real = ids >= 0
+    want = ((pts[ids[real]].astype(np.int64) - queries[0].astype(np.int64)) ** 2).sum(axis=1)
+    assert (tot[real] == want).all(), "batched output does not decrypt to the true distances"
 
     # ------------------------------------------------- per-phase (roofline)
     nat.sanns_profile_enable(ctx.handle, True)
@@ -166,10 +181,12 @@ def main():
     mac_ms = phases["mac"]
     mac_ops = 3 * mulacc  # 32x32->64 multiply-adds: Karatsuba on 27-bit halves
     mac_tops = mac_ops / (mac_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": "k_mac_lds", "achieved": round(mac_tops, 3),
+    roofline = {"bound": "alu", "kernel": "k_mac_lds" if Q > 1 else "k_mac",
+                "achieved": round(mac_tops, 3),
                 "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s (32-bit VALU lane-ops)",
                 "frac": round(mac_tops / VALU_PEAK_TOPS, 4),
-                "traffic": recorded_traffic("k_mac_lds"), "traffic_unit": "bytes/launch",
+                "traffic": recorded_traffic("k_mac_lds") if (w.cid == 2 and Q == 64) else None,
+                "traffic_unit": "bytes/launch",
                 "avg_ms": round(mac_ms, 4),
                 "algorithmic": f"{mac_ops:.4g} ops = 3 x {mulacc:.4g} modular mul-acc"}
     log(f"phases (ms): {phases}")
@@ -216,12 +233,16 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, pts, slot, queries[0], N, L, t)
 
+    kind = "uint8" if pts.dtype == np.uint8 else "int8"
+    headline = w.cid == 2 and Q == 64 and n == 1_000_000
     line = {
-        "metric": METRIC, "value": round(value, 1), "unit": UNIT, "n_gpus": 1,
+        "metric": METRIC if headline else
+        f"encrypted distances/s at {n:,}x{d} {kind}, {Q} queries per step",
+        "value": round(value, 1), "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": f"batched linear scan: {n:,} x {d} uint8 Gaussian-mixture "
+        "config": {"workload": f"batched linear scan: {n:,} x {d} {kind} ({w.gen}) "
                                f"database, {Q} encrypted queries per step, BFV N={N}, "
                                f"L={L} x 54-bit primes, t={t}",
                    "n": n, "d": d, "queries_per_step": Q, "N": N, "L": L, "t": t,
@@ -234,11 +255,252 @@ def main():
                     "fused_query_p50_ms": fused["query_p50_ms"] if fused else None,
                     "fused_query_p99_ms": fused["query_p99_ms"] if fused else None},
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
-        "roofline": roofline,
+        "roofline": roofline if Q > 1 or not fused else fused["roofline"],
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
     ctx.close()
+    return line
+
+
+def encrypt_pool(ctx, queries, seed, dev):
+    """Client-side encryption of a pool of queries (not timed)."""
+    import torch
+    from paper_1904_02033_amd import stage
+    Q, d = queries.shape
+    sk = torch.as_tensor(synthdata.gen_secret(ctx.N, seed)).to(dev)
+    a = synthdata.gen_uniform_a(ctx.qs, ctx.N, Q * d, seed + 1)
+    e = synthdata.gen_cbd_error(ctx.N, Q * d, seed + 1)
+    ct = stage.encrypt_query(ctx, sk, torch.as_tensor(queries.astype(np.int32)).to(dev),
+                             torch.as_tensor(a).to(dev), torch.as_tensor(e).to(dev))
+    torch.cuda.synchronize()
+    return sk, ct
+
+
+def clustered_world(dev, n_clusters=16384, total=9_900_000, stash=100_000):
+    from paper_1904_02033_amd import clustered, stage
+    w = synthdata.WORKLOADS[4]
+    t0 = time.time()
+    cdb = synthdata.gen_clustered(n_clusters=n_clusters, total_clustered=total, stash=stash,
+                                  d=w.d, seed=synthdata.SEED_DATA + 4)
+    ctx = stage.Context(w.N, w.L, w.t_bits)
+    srv = clustered.ClusteredServer(
+        ctx, cdb.points, cdb.cluster_sizes, cdb.centers, cdb.stash_size,
+        synthdata.gen_perm(n_clusters, synthdata.SEED_PERM + 4),
+        synthdata.gen_perm(stash, synthdata.SEED_PERM + 40),
+        synthdata.gen_mask_key(synthdata.SEED_MASK + 4),
+        synthdata.gen_mask_key(synthdata.SEED_MASK + 40))
+    log(f"clustered setup {time.time() - t0:.1f}s: {len(cdb.points):,} points, "
+        f"{srv.db.n_chunks} chunks, {srv.cdb.n_chunks} centre chunks")
+    return w, cdb, ctx, srv
+
+
+def client_select_fn(srv, sk, queries_of, u):
+    """Client step between the two phases: decrypt the centre shares and
+    pick the u closest clusters per query (cleartext stand-in)."""
+    import torch
+    from paper_1904_02033_amd import clustered, stage
+
+    side = torch.cuda.Stream()
+
+    def select(req_or_pair, R=None):
+        with torch.cuda.stream(side):
+            return _select(req_or_pair, R)
+
+    def _select(req_or_pair, R=None):
+        if R is not None:  # serving loop: a request
+            out, share, _ = req_or_pair.outputs["centres"]
+            qs = queries_of(req_or_pair)
+        else:
+            out, share, qs = req_or_pair
+        ctx = srv.ctx
+        C = srv.cdb.n_chunks
+        qn2 = ((qs.astype(np.int64) ** 2).sum(axis=1) % ctx.t).astype(np.uint32)
+        cl = stage.decrypt_shares(ctx, sk, out.contiguous(),
+                                  torch.as_tensor(np.repeat(qn2, C)).to(out.device))
+        cl, sh = cl.cpu().numpy(), share.cpu().numpy()
+        sel = []
+        for q in range(len(qs)):
+            dist = ((cl[q * C:(q + 1) * C].astype(np.int64) + sh[q * C:(q + 1) * C])
+                    % ctx.t).reshape(-1)
+            sel.append(clustered.select_clusters(dist, srv.center_slot, u))
+        return sel
+    return select
+
+
+def run_clustered(args):
+    """Clustered sublinear form: 10M x 96 int8 in 16,384 Zipf clusters plus
+    a 1% stash; 32 queries per launch, 64 clusters per query."""
+    import torch
+    from paper_1904_02033_amd import clustered, native as nat, stage
+    dev = torch.device("cuda", 0)
+    w, cdb, ctx, srv = clustered_world(dev)
+    Q, u = w.Q, 64
+    queries = synthdata.gen_queries(w, Q)
+    sk, ct = encrypt_pool(ctx, queries, synthdata.SEED_SK + 4, dev)
+    qids = torch.as_tensor(np.arange(Q, dtype=np.uint64)).to(dev)
+    select = client_select_fn(srv, sk, None, u)
+    # phase 1 once to fix the selection (client side between phases)
+    cout, cshare = srv.center_distances(ct, qids)
+    selected = select((cout, cshare, queries))
+    work = srv.work_list(selected)
+    D1 = stage.Distances(ctx, srv.cdb, Q, mode=nat.SANNS_MODE_BATCHED)
+    D2 = stage.Distances(ctx, srv.db, Q, work=work, mode=nat.SANNS_MODE_BATCHED)
+    for _ in range(args.warmup):
+        D1.run(ct, srv.key_centers, qids)
+        D2.run(ct, srv.key_points, qids)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    p1, p2 = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e[0].record()
+        D1.run(ct, srv.key_centers, qids)
+        e[1].record()
+        D2.run(ct, srv.key_points, qids)
+        e[2].record()
+        torch.cuda.synchronize()
+        p1.append(e[0].elapsed_time(e[1]))
+        p2.append(e[1].elapsed_time(e[2]))
+    dt = (time.perf_counter() - t0) / args.steps
+    srv.ctx.device_status()
+    req_pairs = srv.requested_pairs(selected) + Q * srv.n_clusters
+    slots = len(work) * ctx.N + Q * srv.cdb.n_chunks * ctx.N
+    # spot check: one query's selected-cluster distances reconstruct exactly
+    q = 0
+    rows = np.nonzero(work[:, 0] == q)[0][:2]
+    qn2 = np.array([int((queries[q].astype(np.int64) ** 2).sum()) % ctx.t] * len(rows),
+                   dtype=np.uint32)
+    cl = stage.decrypt_shares(ctx, sk, D2.ct_out[rows[0]:rows[-1] + 1].contiguous(),
+                              torch.as_tensor(qn2).to(dev)).cpu().numpy()
+    sh = D2.share[rows[0]:rows[-1] + 1].cpu().numpy()
+    for i, m in enumerate(rows):
+        ids = srv.layout.slot_point[work[m, 1] * ctx.N:(work[m, 1] + 1) * ctx.N]
+        real = ids >= 0
+        want = ((cdb.points[ids[real]].astype(np.int64) - queries[q]) ** 2).sum(axis=1)
+        assert (((cl[i].astype(np.int64) + sh[i]) % ctx.t)[real] == want).all()
+    lens = np.bincount(work[:, 0], minlength=Q)
+    return {
+        "metric": "encrypted distances/s, clustered sublinear form (requested pairs)",
+        "value": round(req_pairs / dt, 1), "unit": UNIT,
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"clustered: {len(cdb.points):,} x {w.d} int8, "
+                               f"{srv.n_clusters} Zipf clusters + {cdb.stash_size:,} stash, "
+                               f"{Q} queries x {u} clusters, N={ctx.N}, L={ctx.L}, t={ctx.t}",
+                   "chunks": srv.db.n_chunks, "centre_chunks": srv.cdb.n_chunks},
+        "requested_pairs_per_step": int(req_pairs),
+        "slots_processed_per_step": int(slots),
+        "phase1_ms_p50": round(pct(p1, 50), 3), "phase2_ms_p50": round(pct(p2, 50), 3),
+        "chunks_per_query": {"min": int(lens.min()), "median": float(np.median(lens)),
+                             "max": int(lens.max())},
+        "slot_throughput": round(slots / dt, 1),
+    }
+
+
+def run_serving(args):
+    """Serving: Poisson arrivals against three resident databases; p50/p99
+    arrival-to-shares latency and distances/s, against the per-query path."""
+    import torch
+    from paper_1904_02033_amd import native as nat, serve, stage
+    dev = torch.device("cuda", 0)
+    wA, wB = synthdata.WORKLOADS[2], synthdata.WORKLOADS[3]
+    ctxA = stage.Context(wA.N, wA.L, wA.t_bits)
+    ptsA = synthdata.gen_points(wA, n=100_000, seed=synthdata.SEED_DATA + 5)
+    dbA = stage.encode_db(ctxA, ptsA, stage.linear_slot_map(
+        len(ptsA), ctxA.N, synthdata.gen_perm(len(ptsA), synthdata.SEED_PERM + 5)))
+    w4, cdb, ctxB, srv = clustered_world(dev)
+    ptsB = synthdata.gen_points(wB)
+    dbB = stage.encode_db(ctxB, ptsB, stage.linear_slot_map(
+        len(ptsB), ctxB.N, synthdata.gen_perm(len(ptsB), synthdata.SEED_PERM + 3)))
+    pool = 64
+    qA = synthdata.gen_queries(wA, pool)
+    qB = synthdata.gen_queries(wB, pool)
+    skA, ctA = encrypt_pool(ctxA, qA, synthdata.SEED_SK + 5, dev)
+    skB, ctB = encrypt_pool(ctxB, qB, synthdata.SEED_SK + 50, dev)
+    dbs = [serve.ResidentDB("A", ctxA, db=dbA, key=synthdata.gen_mask_key(5001)),
+           serve.ResidentDB("B", ctxB, db=dbB, key=synthdata.gen_mask_key(5002)),
+           serve.ResidentDB("C", ctxB, server=srv, u=64)]
+    n_of = {"A": len(ptsA), "B": len(ptsB)}
+    select = client_select_fn(srv, skB, lambda r: qB[r.pool_rows], 64)
+
+    def make_requests(rate, count, seed, per_query=False):
+        """Requests of the arrival trace; with per_query every request is
+        split into single-query requests that share its arrival time."""
+        arr = synthdata.gen_arrivals(count, rate, n_dbs=3, max_q=64, seed=seed)
+        reqs, qid = [], 1 << 20
+        for r in arr:
+            name = "ABC"[r.db]
+            ct_all = ctA if name == "A" else ctB
+            parts = [(i, i + 1) for i in range(r.Q)] if per_query else [(0, r.Q)]
+            for a, b in parts:
+                req = serve.Request(r.rid, name, ct_all[a:b],
+                                    np.arange(qid + a, qid + b, dtype=np.uint64), r.k,
+                                    arrival=r.arrival_s)
+                req.pool_rows = np.arange(a, b) % pool
+                reqs.append(req)
+            qid += r.Q
+        return reqs
+
+    def distances_of(req):
+        if req.db == "C":
+            return req.Q * srv.n_clusters + srv.requested_pairs(req.selected)
+        return req.Q * n_of[req.db]
+
+    def serve_trace(reqs, max_batch, inflight, realtime):
+        s = serve.Server(dbs, hbm_budget=64 << 30, max_inflight=inflight,
+                         max_batch_queries=max_batch, client_select=select,
+                         keep_outputs=False)
+        t0 = time.perf_counter()
+        done = s.run(reqs, realtime=realtime)
+        wall = time.perf_counter() - t0
+        # a request split into parts completes when its last part does
+        by_rid = {}
+        for r in done:
+            a, dn = by_rid.get(r.rid, (r.arrival, r.done))
+            by_rid[r.rid] = (min(a, r.arrival), max(dn, r.done))
+        lat = np.array([1e3 * (dn - a) for a, dn in by_rid.values()])
+        st = {"requests": len(by_rid), "p50_ms": round(pct(lat, 50), 3),
+              "p99_ms": round(pct(lat, 99), 3), "mean_ms": round(float(lat.mean()), 3)}
+        st["distances_per_s"] = round(sum(distances_of(r) for r in done) / wall, 1)
+        st["wall_s"] = round(wall, 3)
+        st["launches"] = s.launches
+        st["peak_hbm_bytes"] = s.peak_used
+        return st
+
+    nreq = args.serving_requests
+    # warm-up, then capacity: every request present at t = 0
+    serve_trace(make_requests(1000.0, 20, synthdata.SEED_ARR + 50), 64, 3, False)
+    cap = serve_trace(make_requests(1000.0, nreq, synthdata.SEED_ARR + 5), 64, 3, False)
+    cap_rate = nreq / cap["wall_s"]
+    log(f"serving capacity {cap_rate:.1f} req/s: {cap}")
+    out = {"capacity_req_per_s": round(cap_rate, 2), "saturated": cap}
+    for rho in (0.5, 0.9):
+        st = serve_trace(make_requests(rho * cap_rate, nreq, synthdata.SEED_ARR + 5), 64, 3,
+                         True)
+        log(f"rho={rho}: {st}")
+        out[f"rho_{rho}"] = st
+    # the per-query path: one query per launch, one launch at a time
+    per_q = serve_trace(make_requests(1000.0, max(10, nreq // 10), synthdata.SEED_ARR + 5,
+                                      per_query=True), 1, 1, False)
+    log(f"per-query path (saturated): {per_q}")
+    out["per_query_path_saturated"] = per_q
+    return {
+        "metric": "serving: p50/p99 arrival-to-shares latency and encrypted distances/s",
+        "value": out["rho_0.9"]["distances_per_s"], "unit": UNIT, "n_gpus": 1,
+        "steps": nreq, "warmup": 20, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "serving: Poisson arrivals, Q ~ U{1..64}, k in {1,10,100}, "
+                               "databases 100K x 128 uint8, 1M x 96 int8, clustered 10M x 96 "
+                               "int8 (64 clusters per query); fused batched launches, "
+                               "3 in flight, <= 64 queries per launch"},
+        "latency": {"p50_ms_rho_0.9": out["rho_0.9"]["p50_ms"],
+                    "p99_ms_rho_0.9": out["rho_0.9"]["p99_ms"],
+                    "p50_ms_rho_0.5": out["rho_0.5"]["p50_ms"],
+                    "p99_ms_rho_0.5": out["rho_0.5"]["p99_ms"]},
+        "serving": out,
+        "batched_vs_per_query": round(cap["distances_per_s"] / per_q["distances_per_s"], 2),
+    }
 
 
 def run_fused(args, ctx, db, F, ct1, key, q1, n, d, L, C, N):

@@ -73,6 +73,7 @@ class _Job:
 
 @dataclasses.dataclass
 class _Launch:
+    slot: int
     jobs: List[_Job]
     dbname: str
     stage: str
@@ -92,7 +93,9 @@ class AdmissionError(RuntimeError):
 class Server:
     def __init__(self, dbs: Sequence[ResidentDB], hbm_budget: int, max_inflight: int = 3,
                  max_batch_queries: int = 64, mode: int = nat.SANNS_MODE_FUSED,
-                 client_select: Optional[Callable] = None):
+                 client_select: Optional[Callable] = None, keep_outputs: bool = True):
+        """keep_outputs=False releases each request's output buffers when it
+        completes (as a server does once the shares have been sent)."""
         self.dbs = {d.name: d for d in dbs}
         self.hbm_budget = int(hbm_budget)
         self.max_inflight = max_inflight
@@ -101,7 +104,12 @@ class Server:
         self.client_select = client_select
         self.queues: Dict[tuple, collections.deque] = collections.defaultdict(collections.deque)
         self.inflight: List[_Launch] = []
+        self.keep_outputs = keep_outputs
         self.streams = [torch.cuda.Stream() for _ in range(max_inflight)]
+        # per launch slot: reusable workspace and query staging buffers
+        self.pool_ws: List[Optional[torch.Tensor]] = [None] * max_inflight
+        self.pool_ct: List[Optional[torch.Tensor]] = [None] * max_inflight
+        self.busy = [False] * max_inflight
         self.used = 0
         self.peak_used = 0
         self.launches = 0
@@ -205,9 +213,19 @@ class Server:
                     return
             self._launch(dbname, st, jobs)
 
+    def _grow(self, pool: list, slot: int, nbytes: int, like: torch.Tensor) -> torch.Tensor:
+        buf = pool[slot]
+        if buf is None or buf.numel() < nbytes:
+            buf = torch.empty(max(nbytes, int(1.25 * (0 if buf is None else buf.numel()))),
+                              dtype=torch.uint8, device=like.device)
+            pool[slot] = buf
+        return buf
+
     def _launch(self, dbname: str, st: str, jobs: List[_Job]):
         R = self.dbs[dbname]
-        stream = self.streams[self.launches % len(self.streams)]
+        slot = self.busy.index(False)
+        self.busy[slot] = True
+        stream = self.streams[slot]
         self.launches += 1
         cts = [j.req.ct for j in jobs]
         qids = np.concatenate([j.req.qids for j in jobs]).astype(np.uint64)
@@ -221,20 +239,33 @@ class Server:
         else:
             desc_db, key = R.db, R.key
         with torch.cuda.stream(stream):
-            ct = cts[0] if len(cts) == 1 else torch.cat(cts, dim=0)
+            if len(cts) == 1:
+                ct = cts[0]
+            else:
+                shape = (sum(c.shape[0] for c in cts),) + tuple(cts[0].shape[1:])
+                nb = int(np.prod(shape)) * 8
+                ct = self._grow(self.pool_ct, slot, nb, cts[0])[:nb].view(torch.uint64)
+                ct = ct.view(shape)
+                torch.cat(cts, dim=0, out=ct)
             qd = torch.as_tensor(qids).to(ct.device, non_blocking=False)
-            D = stage.Distances(R.ctx, desc_db, ct.shape[0], work=work, mode=self.mode)
+            need = nat.sanns_distances_workspace(R.ctx.handle, desc_db.desc, ct.shape[0],
+                                                 ct.shape[0] * desc_db.n_chunks
+                                                 if work is None else len(work), self.mode)
+            ws = self._grow(self.pool_ws, slot, need, ct)
+            D = stage.Distances(R.ctx, desc_db, ct.shape[0], work=work, mode=self.mode,
+                                workspace=ws)
             out, share = D.run(ct, key, qd, stream)
             ev = torch.cuda.Event()
             ev.record(stream)
         nbytes = D.ws_bytes + out.numel() * 8 + share.numel() * 4
         self.used += nbytes
         self.peak_used = max(self.peak_used, self.used)
-        self.inflight.append(_Launch(jobs, dbname, st, nbytes, ev, stream, out, share, work,
-                                     [ct, qd, D]))
+        self.inflight.append(_Launch(slot, jobs, dbname, st, nbytes, ev, stream, out, share,
+                                     work, [ct, qd, D]))
 
     def _retire(self, lx: _Launch):
         self.used -= lx.bytes
+        self.busy[lx.slot] = False
         C = self._n_chunks(lx.dbname, lx.stage)
         row = 0
         q0 = 0
@@ -257,9 +288,13 @@ class Server:
             if lx.stage == "centres":
                 j.req.phase = 1
                 j.req.selected = self.client_select(j.req, self.dbs[j.req.db])
+                if not self.keep_outputs:
+                    j.req.outputs.pop("centres")
                 self.queues[(j.req.db, "points")].append(_Job(j.req, "points"))
             else:
                 j.req.done = self.now()
+                if not self.keep_outputs:
+                    j.req.outputs.clear()
                 self.completed.append(j.req)
 
 

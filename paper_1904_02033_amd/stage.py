@@ -133,13 +133,19 @@ class Distances:
     """Output and workspace buffers of sanns_distances for a fixed (Q, M)."""
 
     def __init__(self, ctx: Context, db: Database, Q: int,
-                 work: Optional[np.ndarray] = None, mode: int = nat.SANNS_MODE_FUSED):
+                 work: Optional[np.ndarray] = None, mode: int = nat.SANNS_MODE_FUSED,
+                 workspace: Optional[torch.Tensor] = None):
+        """workspace: optional uint8 device tensor of at least the required
+        size, reused instead of a fresh allocation."""
         self.ctx, self.db, self.Q, self.mode = ctx, db, Q, mode
         self.work = None if work is None else np.ascontiguousarray(work, dtype=np.uint32)
         self.M = Q * db.n_chunks if work is None else len(self.work)
         dev = db.mem.device
         self.ws_bytes = nat.sanns_distances_workspace(ctx.handle, db.desc, Q, self.M, mode)
-        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        if workspace is not None and workspace.numel() >= self.ws_bytes:
+            self.ws = workspace[:self.ws_bytes]
+        else:
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
         self.ct_out = torch.empty((self.M, 2, ctx.L, ctx.N), dtype=torch.uint64, device=dev)
         self.share = torch.empty((self.M, ctx.N), dtype=torch.uint32, device=dev)
 

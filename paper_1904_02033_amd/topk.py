@@ -46,6 +46,14 @@ def naive_topk(values: np.ndarray, ids: np.ndarray, k: int) -> Tuple[np.ndarray,
     kk = min(k, n)
     thresh = np.partition(values, kk - 1)[kk - 1]
     cand = np.nonzero(values <= thresh)[0]
+    cv = values[cand]
+    if len(np.unique(cv)) == len(cv):
+        # distinct values: Algorithm 1's list is the candidates in value order
+        o = np.argsort(cv, kind="stable")[:kk]
+        out_v = np.full(k, np.iinfo(np.int64).max, dtype=np.int64)
+        out_i = np.full(k, -1, dtype=np.int64)
+        out_v[:kk], out_i[:kk] = cv[o], ids[cand[o]]
+        return out_v, out_i
     opt_v = [np.iinfo(np.int64).max] * k
     opt_i = [-1] * k
     for j in cand:

@@ -220,11 +220,13 @@ def gen_clustered(n_clusters: int = 16384, total_clustered: int = 9_900_000,
     pts = np.empty((n, d), dtype=np.int8)
     owner = np.concatenate([np.repeat(np.arange(n_clusters), sizes),
                             g.integers(0, n_clusters, size=stash)])
+    cen32 = cen.astype(np.float32)
     for s in range(0, n, block):
         e = min(n, s + block)
-        x = cen[owner[s:e]] + g.normal(0.0, sigma_c, size=(e - s, d))
+        x = cen32[owner[s:e]] + np.float32(sigma_c) * g.standard_normal(
+            size=(e - s, d), dtype=np.float32)
         x /= np.linalg.norm(x, axis=1, keepdims=True)
-        pts[s:e] = np.clip(np.rint(x * 127.0), -127, 127).astype(np.int8)
+        pts[s:e] = np.clip(np.rint(x * np.float32(127.0)), -127, 127).astype(np.int8)
     qc = np.clip(np.rint(cen * 127.0), -127, 127).astype(np.int8)
     return ClusteredDB(pts, sizes, qc, stash)
 
