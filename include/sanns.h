@@ -244,7 +244,8 @@ sanns_status sanns_device_status(sanns_ctx *ctx, void *stream);
 
 /* Fix the multiply-accumulate schedule (used by the autotuner):
  *   lds_variant  LDS-staged kernel used for batches of >= 2 queries against
- *                every chunk (work == NULL): 1..8, or 0 for the default;
+ *                every chunk (work == NULL): 1..11 (register-staged) or 21..27
+ *                (direct-to-LDS staged), or 0 for the default;
  *   qt x ct      register tile (queries x chunks per thread) used for every
  *                other call: 1x1, 1x2, 1x4, 1x8, 2x2, 2x4, 4x2, 2x3, 3x2, or
  *                0x0 for the automatic choice.

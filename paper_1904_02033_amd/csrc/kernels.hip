@@ -69,10 +69,12 @@ __device__ __forceinline__ void scale_ninv(uint64_t (&v)[16], const Prime& P) {
 // forward / inverse transforms of independent polynomials
 // --------------------------------------------------------------------------
 
-// One polynomial per workgroup; polynomial p uses limb p % L.
+// One polynomial per workgroup; polynomial p uses limb p % L.  With split
+// set the output residues are stored as their 27-bit halves (uint2), the
+// form the multiply-accumulate kernels consume.
 __global__ void __launch_bounds__(1024)
 k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int logN, int L,
-          PrimeSet ps, TwSet tws, uint32_t* err) {
+          PrimeSet ps, TwSet tws, uint32_t* err, int split) {
   extern __shared__ uint64_t lds[];
   const int tid = threadIdx.x, N = 1 << logN;
   const int p = blockIdx.x, l = p % L;
@@ -89,8 +91,18 @@ k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int logN,
   ntt_fwd(v, lds, logN, tid, tw_fwd(tws, l, N), twp_fwd(tws, l, N), P.q);
   reduce4q(v, P.q);
   uint64_t* dst = out + (size_t)p * N;
+  if (split) {
+    uint2* dst2 = reinterpret_cast<uint2*>(dst);
 #pragma unroll
-  for (int a = 0; a < 16; ++a) dst[fwd_last_index(tid, a, logN)] = v[a];
+    for (int a = 0; a < 16; ++a) {
+      uint2 y;
+      split27(v[a], y.x, y.y);
+      dst2[fwd_last_index(tid, a, logN)] = y;
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 16; ++a) dst[fwd_last_index(tid, a, logN)] = v[a];
+  }
 }
 
 // In-place inverse transform, result multiplied by N^-1 and in [0, q).
@@ -253,7 +265,7 @@ __device__ __forceinline__ MacTile<QT, CT> regular_tile(int y, int Q, int C) {
 
 template <int QT, int CT>
 __global__ void __launch_bounds__(256)
-k_mac(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db,
+k_mac(const uint2* __restrict__ qntt, const uint2* __restrict__ db,
       const MacTile<QT, CT>* __restrict__ tiles, int Q, int d, int L, int logN, int C,
       PrimeSet ps, uint64_t* __restrict__ out) {
   const int N = 1 << logN;
@@ -263,7 +275,7 @@ k_mac(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db,
   const Prime& P = ps.p[l];
   const size_t qstride_i = (size_t)2 * L * N;                 // next coordinate
   const size_t dbstride_i = (size_t)N;
-  const uint64_t* qb[QT];
+  const uint2* qb[QT];
   const uint2* dbb[CT];
 #pragma unroll
   for (int a = 0; a < QT; ++a) qb[a] = qntt + ((size_t)T.q[a] * d * 2 * L + l) * N + s;
@@ -297,14 +309,16 @@ k_mac(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db,
     for (int a = 0; a < QT; ++a)
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        split27(qb[a][i0 * qstride_i + (size_t)c * L * N], x0[a][c], x1[a][c]);
-        x01[a][c] = x0[a][c] + x1[a][c];
+        const uint2 v = qb[a][i0 * qstride_i + (size_t)c * L * N];
+        x0[a][c] = v.x;
+        x1[a][c] = v.y;
+        x01[a][c] = v.x + v.y;
       }
 #pragma unroll
     for (int b = 0; b < CT; ++b) yv[b] = dbb[b][i0 * dbstride_i];
     for (int i = i0; i < i1; ++i) {
       const int inext = i + 1 < i1 ? i + 1 : i;
-      uint64_t xn[QT][2];
+      uint2 xn[QT][2];
       uint2 yn[CT];
 #pragma unroll
       for (int a = 0; a < QT; ++a)
@@ -331,7 +345,8 @@ k_mac(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db,
       for (int a = 0; a < QT; ++a)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          split27(xn[a][c], x0[a][c], x1[a][c]);
+          x0[a][c] = xn[a][c].x;
+          x1[a][c] = xn[a][c].y;
           x01[a][c] = x0[a][c] + x1[a][c];
         }
 #pragma unroll
@@ -364,9 +379,37 @@ k_mac(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db,
 // Blocks are numbered so that every XCD (blocks b with equal b mod 8) walks
 // its own range of (slot tile, limb) pairs, all query/chunk tiles of a pair
 // running back to back, which keeps the pair's operands in that XCD's L2.
-template <int QT, int CT, int QG, int CG, int S, int DI>
+// Fold of the accumulators into residues and the write of the block's
+// outputs (pairs whose query or chunk index falls outside the batch are
+// padding and are not written).
+template <int QT, int CT>
+__device__ __forceinline__ void mac_store(const Acc3 (&acc)[QT][2][CT],
+                                          const uint64_t (&res)[QT][2][CT], bool have_res,
+                                          const Prime& P, int q0, int k0,
+                                          int gq, int gc, int Q, int C, int L, int l, int N,
+                                          int slot, uint64_t* __restrict__ out) {
+#pragma unroll
+  for (int a = 0; a < QT; ++a) {
+    const int q = q0 + gq * QT + a;
+#pragma unroll
+    for (int b = 0; b < CT; ++b) {
+      const int k = k0 + gc * CT + b;
+      if (q >= Q || k >= C) continue;
+      const size_t o = (size_t)q * C + k;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        uint64_t v = acc3_reduce(acc[a][c][b], P);
+        if (have_res) v = addmod(v, res[a][c][b], P.q);
+        out[((o * 2 + c) * L + l) * N + slot] = v;
+      }
+    }
+  }
+}
+
+// WIDE: d > FOLD, partial residues of earlier folds are kept in registers.
+template <int QT, int CT, int QG, int CG, int S, int DI, int UNR, bool WIDE>
 __global__ void __launch_bounds__(S * QG * CG)
-k_mac_lds(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db, int Q, int d, int L,
+k_mac_lds(const uint2* __restrict__ qntt, const uint2* __restrict__ db, int Q, int d, int L,
           int logN, int C, int n_blocks, PrimeSet ps, uint64_t* __restrict__ out) {
   constexpr int QB = QT * QG, CB = CT * CG, NT = S * QG * CG;
   constexpr int FOLD = (255 / DI) * DI;  // coordinates per 64-bit accumulation
@@ -389,42 +432,52 @@ k_mac_lds(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db, int Q
   const int tid = threadIdx.x;
   const int s = tid % S, g = tid / S, gq = g % QG, gc = g / QG;
 
-  // global -> registers for the step starting at coordinate i0
-  uint64_t rq[NQE];
-  uint2 rd[NDE];
-  auto fetch = [&](int i0) {
+  // Staging: thread tid moves words e = tid + u NT of every step.  Their
+  // source addresses for coordinate 0 are computed once; a step at
+  // coordinate i0 adds i0 times the per-coordinate stride.
+  const uint2* qsrc[NQE];
+  int qdi[NQE];
+  const uint2* dsrc[NDE];
+  int ddi[NDE];
 #pragma unroll
-    for (int u = 0; u < NQE; ++u) {
-      const int e = tid + u * NT;
-      const int ss = e % S, r = e / S;
-      const int di = r % DI, qc = r / DI;
-      const int c = qc & 1, qq = qc >> 1;
-      const int q = q0 + qq < Q ? q0 + qq : Q - 1;
-      const int i = i0 + di;
-      rq[u] = (e < QE && i < d)
-                  ? qntt[((((size_t)q * d + i) * 2 + c) * L + l) * N + s0 + ss]
-                  : 0ull;
-    }
+  for (int u = 0; u < NQE; ++u) {
+    const int e = tid + u * NT < QE ? tid + u * NT : QE - 1;
+    const int ss = e % S, r = e / S;
+    const int di = r % DI, qc = r / DI;
+    const int c = qc & 1, qq = qc >> 1;
+    const int q = q0 + qq < Q ? q0 + qq : Q - 1;
+    qdi[u] = tid + u * NT < QE ? di : 1 << 30;
+    qsrc[u] = qntt + ((((size_t)q * d + di) * 2 + c) * L + l) * N + s0 + ss;
+  }
 #pragma unroll
-    for (int u = 0; u < NDE; ++u) {
-      const int e = tid + u * NT;
-      const int ss = e % S, r = e / S;
-      const int di = r % DI, cc = r / DI;
-      const int k = k0 + cc < C ? k0 + cc : C - 1;
-      const int i = i0 + di;
-      rd[u] = (e < DE && i < d) ? db[(((size_t)l * C + k) * d + i) * N + s0 + ss]
-                                : make_uint2(0u, 0u);
-    }
+  for (int u = 0; u < NDE; ++u) {
+    const int e = tid + u * NT < DE ? tid + u * NT : DE - 1;
+    const int ss = e % S, r = e / S;
+    const int di = r % DI, cc = r / DI;
+    const int k = k0 + cc < C ? k0 + cc : C - 1;
+    ddi[u] = tid + u * NT < DE ? di : 1 << 30;
+    dsrc[u] = db + (((size_t)l * C + k) * d + di) * N + s0 + ss;
+  }
+  const size_t qstep = (size_t)2 * L * N, dstep = (size_t)N;
+
+  // Two register sets ring the staged words: while LDS buffer `cur` is
+  // multiplied, the words of the next step are on their way into LDS buffer
+  // cur ^ 1 and those of the step after next are already being loaded.
+  uint2 rqA[NQE], rqB[NQE];
+  uint2 rdA[NDE], rdB[NDE];
+  auto fetch = [&](int i0, uint2 (&rq)[NQE], uint2 (&rd)[NDE]) {
+#pragma unroll
+    for (int u = 0; u < NQE; ++u)
+      rq[u] = i0 + qdi[u] < d ? qsrc[u][(size_t)i0 * qstep] : make_uint2(0u, 0u);
+#pragma unroll
+    for (int u = 0; u < NDE; ++u)
+      rd[u] = i0 + ddi[u] < d ? dsrc[u][(size_t)i0 * dstep] : make_uint2(0u, 0u);
   };
-  auto stash = [&](int buf) {
+  auto stash = [&](int buf, const uint2 (&rq)[NQE], const uint2 (&rd)[NDE]) {
 #pragma unroll
     for (int u = 0; u < NQE; ++u) {
       const int e = tid + u * NT;
-      if (e < QE) {
-        uint2 v;
-        split27(rq[u], v.x, v.y);
-        sq[buf][e] = v;
-      }
+      if (e < QE) sq[buf][e] = rq[u];
     }
 #pragma unroll
     for (int u = 0; u < NDE; ++u) {
@@ -433,27 +486,25 @@ k_mac_lds(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db, int Q
     }
   };
 
-  uint64_t res[QT][2][CT];
   Acc3 acc[QT][2][CT];
 #pragma unroll
   for (int a = 0; a < QT; ++a)
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int b = 0; b < CT; ++b) {
-        res[a][c][b] = 0;
-        acc3_zero(acc[a][c][b]);
-      }
+      for (int b = 0; b < CT; ++b) acc3_zero(acc[a][c][b]);
+  uint64_t res[QT][2][CT];
+  if (WIDE) {
+#pragma unroll
+    for (int a = 0; a < QT; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < CT; ++b) res[a][c][b] = 0;
+  }
 
-  fetch(0);
-  stash(0);
-  __syncthreads();
-  int cur = 0;
-  for (int i0 = 0; i0 < d; i0 += DI) {
-    const bool more = i0 + DI < d;
-    if (more) fetch(i0 + DI);
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll 2
+  auto compute = [&](int cur) {
+#pragma unroll UNR
     for (int di = 0; di < DI; ++di) {
       uint32_t x0[QT][2], x1[QT][2], x01[QT][2];
 #pragma unroll
@@ -479,8 +530,9 @@ k_mac_lds(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db, int Q
           }
       }
     }
-    __builtin_amdgcn_sched_barrier(0);
-    if ((i0 + DI) % FOLD == 0 || !more) {
+  };
+  auto fold = [&](int i0) {
+    if (WIDE && i0 + DI < d && (i0 + DI) % FOLD == 0) {
 #pragma unroll
       for (int a = 0; a < QT; ++a)
 #pragma unroll
@@ -491,23 +543,188 @@ k_mac_lds(const uint64_t* __restrict__ qntt, const uint2* __restrict__ db, int Q
             acc3_zero(acc[a][c][b]);
           }
     }
-    if (more) stash(cur ^ 1);
+  };
+
+  fetch(0, rqA, rdA);
+  if (DI < d) fetch(DI, rqB, rdB);
+  stash(0, rqA, rdA);
+  __syncthreads();
+  int cur = 0;
+  for (int i0 = 0; i0 < d; i0 += 2 * DI) {
+    // step at i0: LDS[cur] holds it, set B holds i0 + DI
+    if (i0 + 2 * DI < d) fetch(i0 + 2 * DI, rqA, rdA);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(cur);
+    __builtin_amdgcn_sched_barrier(0);
+    fold(i0);
+    if (i0 + DI >= d) break;
+    stash(cur ^ 1, rqB, rdB);
+    __syncthreads();
+    cur ^= 1;
+    // step at i0 + DI: LDS[cur] holds it, set A holds i0 + 2 DI
+    if (i0 + 3 * DI < d) fetch(i0 + 3 * DI, rqB, rdB);
+    __builtin_amdgcn_sched_barrier(0);
+    compute(cur);
+    __builtin_amdgcn_sched_barrier(0);
+    fold(i0 + DI);
+    if (i0 + 2 * DI >= d) break;
+    stash(cur ^ 1, rqA, rdA);
     __syncthreads();
     cur ^= 1;
   }
+  mac_store<QT, CT>(acc, res, WIDE, P, q0, k0, gq, gc, Q, C, L, l, N, s0 + s, out);
+}
+
+// Direct-to-LDS variant of k_mac_lds: the staged words go from global
+// memory straight into LDS (global_load_lds, 16 bytes per lane), so no
+// registers are spent on staging and the query words arrive already split.
+// LDS buffer B0/B1 alternate: the next step is loaded into one while the
+// other is multiplied.
+template <int QT, int CT, int QG, int CG, int S, int DI, int UNR, bool WIDE>
+__global__ void __launch_bounds__(S * QG * CG)
+k_mac_dl(const uint2* __restrict__ qntt, const uint2* __restrict__ db, int Q, int d, int L,
+         int logN, int C, int n_blocks, PrimeSet ps, uint64_t* __restrict__ out) {
+  constexpr int QB = QT * QG, CB = CT * CG, NT = S * QG * CG;
+  constexpr int FOLD = (255 / DI) * DI;
+  constexpr int H = S / 2;                            // 16-byte units per row of S slots
+  constexpr int QU = QB * 2 * DI * H, DU = CB * DI * H;  // 16-byte units per step
+  constexpr int NQU = (QU + NT - 1) / NT, NDU = (DU + NT - 1) / NT;
+  __shared__ uint4 sq0[QU], sq1[QU];
+  __shared__ uint4 sd0[DU], sd1[DU];
+  const int N = 1 << logN;
+  const int nqt = (Q + QB - 1) / QB, nct = (C + CB - 1) / CB;
+  const int per_xcd = (n_blocks + 7) >> 3;
+  const int lin = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (lin >= n_blocks) return;
+  const int y = lin % (nqt * nct);
+  const int sl = lin / (nqt * nct);
+  const int l = sl % L, st = sl / L;
+  const int q0 = (y % nqt) * QB, k0 = (y / nqt) * CB;
+  const int s0 = st * S;
+  const Prime& P = ps.p[l];
+  const int tid = threadIdx.x;
+  const int s = tid % S, g = tid / S, gq = g % QG, gc = g / QG;
+  const int wbase = __builtin_amdgcn_readfirstlane(tid) & ~63;
+
+  const uint2* qsrc[NQU];
+  int qdi[NQU];
+  const uint2* dsrc[NDU];
+  int ddi[NDU];
 #pragma unroll
-  for (int a = 0; a < QT; ++a) {
-    const int q = q0 + gq * QT + a;
-    if (q >= Q) continue;
-#pragma unroll
-    for (int b = 0; b < CT; ++b) {
-      const int k = k0 + gc * CT + b;
-      if (k >= C) continue;
-      const size_t o = (size_t)q * C + k;
-#pragma unroll
-      for (int c = 0; c < 2; ++c) out[((o * 2 + c) * L + l) * N + s0 + s] = res[a][c][b];
-    }
+  for (int u = 0; u < NQU; ++u) {
+    const int e = tid + u * NT;
+    const int ee = e < QU ? e : 0;
+    const int pr = ee % H, r = ee / H;
+    const int di = r % DI, qc = r / DI;
+    const int c = qc & 1, qq = qc >> 1;
+    const int q = q0 + qq < Q ? q0 + qq : Q - 1;
+    qdi[u] = e < QU ? di : 1 << 30;
+    qsrc[u] = qntt + ((((size_t)q * d + di) * 2 + c) * L + l) * N + s0 + 2 * pr;
   }
+#pragma unroll
+  for (int u = 0; u < NDU; ++u) {
+    const int e = tid + u * NT;
+    const int ee = e < DU ? e : 0;
+    const int pr = ee % H, r = ee / H;
+    const int di = r % DI, cc = r / DI;
+    const int k = k0 + cc < C ? k0 + cc : C - 1;
+    ddi[u] = e < DU ? di : 1 << 30;
+    dsrc[u] = db + (((size_t)l * C + k) * d + di) * N + s0 + 2 * pr;
+  }
+  const size_t qstep = (size_t)2 * L * N, dstep = (size_t)N;
+  auto issue = [&](int i0, uint4* bq, uint4* bd) {
+#pragma unroll
+    for (int u = 0; u < NQU; ++u)
+      if (i0 + qdi[u] < d)
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(qsrc[u] + (size_t)i0 * qstep),
+            (__attribute__((address_space(3))) void*)(bq + wbase + u * NT), 16, 0, 0);
+#pragma unroll
+    for (int u = 0; u < NDU; ++u)
+      if (i0 + ddi[u] < d)
+        __builtin_amdgcn_global_load_lds(
+            (const void*)(dsrc[u] + (size_t)i0 * dstep),
+            (__attribute__((address_space(3))) void*)(bd + wbase + u * NT), 16, 0, 0);
+  };
+
+  Acc3 acc[QT][2][CT];
+#pragma unroll
+  for (int a = 0; a < QT; ++a)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int b = 0; b < CT; ++b) acc3_zero(acc[a][c][b]);
+  uint64_t res[QT][2][CT];
+  if (WIDE) {
+#pragma unroll
+    for (int a = 0; a < QT; ++a)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int b = 0; b < CT; ++b) res[a][c][b] = 0;
+  }
+  auto compute = [&](const uint4* bq4, const uint4* bd4, int ndi) {
+    const uint2* bq = reinterpret_cast<const uint2*>(bq4);
+    const uint2* bd = reinterpret_cast<const uint2*>(bd4);
+#pragma unroll UNR
+    for (int di = 0; di < ndi; ++di) {
+      uint32_t x0[QT][2], x1[QT][2], x01[QT][2];
+#pragma unroll
+      for (int a = 0; a < QT; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const uint2 v = bq[(((gq * QT + a) * 2 + c) * DI + di) * S + s];
+          x0[a][c] = v.x;
+          x1[a][c] = v.y;
+          x01[a][c] = v.x + v.y;
+        }
+#pragma unroll
+      for (int b = 0; b < CT; ++b) {
+        const uint2 yv = bd[((gc * CT + b) * DI + di) * S + s];
+        const uint32_t y01 = yv.x + yv.y;
+#pragma unroll
+        for (int a = 0; a < QT; ++a)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            acc[a][c][b].lo += mul32x32(x0[a][c], yv.x);
+            acc[a][c][b].hi += mul32x32(x1[a][c], yv.y);
+            acc[a][c][b].mid += mul32x32(x01[a][c], y01);
+          }
+      }
+    }
+  };
+  auto fold = [&](int i0) {
+    if (WIDE && i0 + DI < d && (i0 + DI) % FOLD == 0) {
+#pragma unroll
+      for (int a = 0; a < QT; ++a)
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int b = 0; b < CT; ++b) {
+            res[a][c][b] = addmod(res[a][c][b], acc3_reduce(acc[a][c][b], P), P.q);
+            acc3_zero(acc[a][c][b]);
+          }
+    }
+  };
+
+  issue(0, sq0, sd0);
+  __builtin_amdgcn_s_waitcnt(0);  // all counters: the first step has landed
+  __syncthreads();
+  for (int i0 = 0; i0 < d; i0 += 2 * DI) {
+    if (i0 + DI < d) issue(i0 + DI, sq1, sd1);
+    compute(sq0, sd0, d - i0 < DI ? d - i0 : DI);
+    fold(i0);
+    if (i0 + DI >= d) break;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (i0 + 2 * DI < d) issue(i0 + 2 * DI, sq0, sd0);
+    compute(sq1, sd1, d - i0 - DI < DI ? d - i0 - DI : DI);
+    fold(i0 + DI);
+    if (i0 + 2 * DI >= d) break;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  mac_store<QT, CT>(acc, res, WIDE, P, q0, k0, gq, gc, Q, C, L, l, N, s0 + s, out);
 }
 
 // --------------------------------------------------------------------------
@@ -768,7 +985,7 @@ k_decrypt(const uint64_t* __restrict__ ct, const uint64_t* __restrict__ sk_ntt,
 
 // tmp[c][l][j] = c_hat_i[c][l][j] g_hat_{i,k}[l][j]  (one query coordinate)
 __global__ void __launch_bounds__(256)
-k_mult_plain(const uint64_t* __restrict__ cq, const uint2* __restrict__ db, int i, int k,
+k_mult_plain(const uint2* __restrict__ cq, const uint2* __restrict__ db, int i, int k,
              int d, int C, int L, int logN, PrimeSet ps, uint64_t* __restrict__ tmp) {
   const int N = 1 << logN;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -777,7 +994,8 @@ k_mult_plain(const uint64_t* __restrict__ cq, const uint2* __restrict__ db, int 
   const Prime& P = ps.p[l];
   const uint2 y = db[(((size_t)l * C + k) * d + i) * N + j];
   const uint64_t b = ((uint64_t)y.y << 27) | y.x;
-  tmp[g] = mulmod(cq[g], b, P);
+  const uint2 x = cq[g];
+  tmp[g] = mulmod(((uint64_t)x.y << 27) | x.x, b, P);
 }
 
 // acc[c][l][j] += tmp[c][l][j]
@@ -816,11 +1034,11 @@ static inline size_t ntt_lds_bytes(int logN) {
 }
 
 hipError_t launch_ntt_fwd(const uint64_t* in, uint64_t* out, int n_polys, int logN, int L,
-                          const PrimeSet& ps, const TwSet& tws, uint32_t* err,
+                          const PrimeSet& ps, const TwSet& tws, uint32_t* err, int split,
                           hipStream_t st) {
   if (n_polys <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_ntt_fwd, dim3(n_polys), dim3(1 << (logN - 4)), ntt_lds_bytes(logN),
-                     st, in, out, logN, L, ps, tws, err);
+                     st, in, out, logN, L, ps, tws, err, split);
   return hipGetLastError();
 }
 
@@ -853,7 +1071,7 @@ hipError_t launch_intt_mask(uint64_t* ct, const uint32_t* share, const uint32_t*
 }
 
 template <int QT, int CT>
-static hipError_t launch_mac_t(const uint64_t* qntt, const uint2* db, const void* tiles,
+static hipError_t launch_mac_t(const uint2* qntt, const uint2* db, const void* tiles,
                                int n_tiles, int Q, int d, int L, int logN, int C,
                                const PrimeSet& ps, uint64_t* out, hipStream_t st) {
   const int N = 1 << logN;
@@ -872,7 +1090,7 @@ size_t mac_tile_bytes(int QT, int CT) {
   return 0;
 }
 
-hipError_t launch_mac(int QT, int CT, const uint64_t* qntt, const uint2* db, const void* tiles,
+hipError_t launch_mac(int QT, int CT, const uint2* qntt, const uint2* db, const void* tiles,
                       int n_tiles, int Q, int d, int L, int logN, int C, const PrimeSet& ps,
                       uint64_t* out, hipStream_t st) {
   if (n_tiles <= 0) return hipSuccess;
@@ -884,8 +1102,8 @@ hipError_t launch_mac(int QT, int CT, const uint64_t* qntt, const uint2* db, con
   return hipErrorInvalidValue;
 }
 
-template <int QT, int CT, int QG, int CG, int S, int DI>
-static hipError_t launch_mac_lds_t(const uint64_t* qntt, const uint2* db, int Q, int d, int L,
+template <int QT, int CT, int QG, int CG, int S, int DI, int UNR>
+static hipError_t launch_mac_lds_t(const uint2* qntt, const uint2* db, int Q, int d, int L,
                                    int logN, int C, const PrimeSet& ps, uint64_t* out,
                                    hipStream_t st) {
   constexpr int QB = QT * QG, CB = CT * CG;
@@ -894,19 +1112,47 @@ static hipError_t launch_mac_lds_t(const uint64_t* qntt, const uint2* db, int Q,
   const long nb = (long)(N / S) * L * ((Q + QB - 1) / QB) * ((C + CB - 1) / CB);
   if (nb > 0x7fffffffL) return hipErrorInvalidValue;
   const int per_xcd = (int)((nb + 7) / 8);
-  hipLaunchKernelGGL((k_mac_lds<QT, CT, QG, CG, S, DI>), dim3(per_xcd * 8), dim3(S * QG * CG), 0,
-                     st, qntt, db, Q, d, L, logN, C, (int)nb, ps, out);
+  if (d > (255 / DI) * DI)
+    hipLaunchKernelGGL((k_mac_lds<QT, CT, QG, CG, S, DI, UNR, true>), dim3(per_xcd * 8),
+                       dim3(S * QG * CG), 0, st, qntt, db, Q, d, L, logN, C, (int)nb, ps, out);
+  else
+    hipLaunchKernelGGL((k_mac_lds<QT, CT, QG, CG, S, DI, UNR, false>), dim3(per_xcd * 8),
+                       dim3(S * QG * CG), 0, st, qntt, db, Q, d, L, logN, C, (int)nb, ps, out);
   return hipGetLastError();
 }
 
-hipError_t launch_mac_lds(int variant, const uint64_t* qntt, const uint2* db, int Q, int d, int L,
+template <int QT, int CT, int QG, int CG, int S, int DI, int UNR>
+static hipError_t launch_mac_dl_t(const uint2* qntt, const uint2* db, int Q, int d, int L,
+                                  int logN, int C, const PrimeSet& ps, uint64_t* out,
+                                  hipStream_t st) {
+  constexpr int QB = QT * QG, CB = CT * CG;
+  const int N = 1 << logN;
+  if (N % S) return hipErrorInvalidValue;
+  const long nb = (long)(N / S) * L * ((Q + QB - 1) / QB) * ((C + CB - 1) / CB);
+  if (nb > 0x7fffffffL) return hipErrorInvalidValue;
+  const int per_xcd = (int)((nb + 7) / 8);
+  if (d > (255 / DI) * DI)
+    hipLaunchKernelGGL((k_mac_dl<QT, CT, QG, CG, S, DI, UNR, true>), dim3(per_xcd * 8),
+                       dim3(S * QG * CG), 0, st, qntt, db, Q, d, L, logN, C, (int)nb, ps, out);
+  else
+    hipLaunchKernelGGL((k_mac_dl<QT, CT, QG, CG, S, DI, UNR, false>), dim3(per_xcd * 8),
+                       dim3(S * QG * CG), 0, st, qntt, db, Q, d, L, logN, C, (int)nb, ps, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mac_lds(int variant, const uint2* qntt, const uint2* db, int Q, int d, int L,
                           int logN, int C, const PrimeSet& ps, uint64_t* out, hipStream_t st) {
   switch (variant) {
-#define SANNS_LDS_CASE(id, qt, ct, qg, cg, s, di) \
-  case id:                                        \
-    return launch_mac_lds_t<qt, ct, qg, cg, s, di>(qntt, db, Q, d, L, logN, C, ps, out, st);
+#define SANNS_LDS_CASE(id, qt, ct, qg, cg, s, di, unr) \
+  case id:                                             \
+    return launch_mac_lds_t<qt, ct, qg, cg, s, di, unr>(qntt, db, Q, d, L, logN, C, ps, out, st);
     SANNS_MAC_LDS_VARIANTS(SANNS_LDS_CASE)
 #undef SANNS_LDS_CASE
+#define SANNS_DL_CASE(id, qt, ct, qg, cg, s, di, unr) \
+  case id:                                            \
+    return launch_mac_dl_t<qt, ct, qg, cg, s, di, unr>(qntt, db, Q, d, L, logN, C, ps, out, st);
+    SANNS_MAC_DL_VARIANTS(SANNS_DL_CASE)
+#undef SANNS_DL_CASE
     default:
       return hipErrorInvalidValue;
   }
@@ -914,10 +1160,11 @@ hipError_t launch_mac_lds(int variant, const uint64_t* qntt, const uint2* db, in
 
 int mac_lds_min_n(int variant) {
   switch (variant) {
-#define SANNS_LDS_S(id, qt, ct, qg, cg, s, di) \
+#define SANNS_LDS_S(id, qt, ct, qg, cg, s, di, unr) \
   case id:                                     \
     return s;
     SANNS_MAC_LDS_VARIANTS(SANNS_LDS_S)
+    SANNS_MAC_DL_VARIANTS(SANNS_LDS_S)
 #undef SANNS_LDS_S
     default:
       return 0;
@@ -965,7 +1212,7 @@ hipError_t launch_decrypt(const uint64_t* ct, int M, const uint64_t* sk_ntt,
   return hipGetLastError();
 }
 
-hipError_t launch_mult_plain(const uint64_t* cq, const uint2* db, int i, int k, int d, int C,
+hipError_t launch_mult_plain(const uint2* cq, const uint2* db, int i, int k, int d, int C,
                              int L, int logN, const PrimeSet& ps, uint64_t* tmp,
                              hipStream_t st) {
   const int total = 2 * L * (1 << logN);

@@ -9,8 +9,11 @@ namespace sanns {
 #define SANNS_MAC_SHAPES(X) \
   X(1, 1) X(1, 2) X(1, 4) X(1, 8) X(2, 2) X(2, 4) X(4, 2) X(2, 3) X(3, 2)
 
+// split: store the NTT residues as 27-bit halves (uint2) for the
+// multiply-accumulate kernels.
 hipError_t launch_ntt_fwd(const uint64_t* in, uint64_t* out, int n_polys, int logN, int L,
-                          const PrimeSet& ps, const TwSet& tws, uint32_t* err, hipStream_t st);
+                          const PrimeSet& ps, const TwSet& tws, uint32_t* err, int split,
+                          hipStream_t st);
 hipError_t launch_ntt_inv(uint64_t* io, int n_polys, int logN, int L, const PrimeSet& ps,
                           const TwSet& tws, hipStream_t st);
 hipError_t launch_masks(const MaskKey& K, const uint64_t* qids, const uint32_t* work, int C,
@@ -20,24 +23,37 @@ hipError_t launch_intt_mask(uint64_t* ct, const uint32_t* share, const uint32_t*
                             const uint32_t* work, int C, int M, int logN, int L, uint32_t t,
                             const PrimeSet& ps, const TwSet& tws, hipStream_t st);
 // tiles == NULL: every query against every chunk (Q x C outputs, m = q C + k).
-hipError_t launch_mac(int QT, int CT, const uint64_t* qntt, const uint2* db, const void* tiles,
+hipError_t launch_mac(int QT, int CT, const uint2* qntt, const uint2* db, const void* tiles,
                       int n_tiles, int Q, int d, int L, int logN, int C, const PrimeSet& ps,
                       uint64_t* out, hipStream_t st);
 size_t mac_tile_bytes(int QT, int CT);  // 0 for a shape that is not built
 
 // LDS-staged variants of the all-pairs multiply-accumulate:
-// X(id, QT, CT, QG, CG, S, DI), block = S slots x QG x CG threads covering
-// QG QT queries x CG CT chunks.
+// X(id, QT, CT, QG, CG, S, DI, UNR), block = S slots x QG x CG threads
+// covering QG QT queries x CG CT chunks, DI coordinates per staging step,
+// UNR = unroll of the coordinate loop.
 #define SANNS_MAC_LDS_VARIANTS(X)      \
-  X(1, 2, 4, 4, 4, 32, 4)              \
-  X(2, 2, 4, 2, 4, 32, 4)              \
-  X(3, 2, 4, 4, 2, 32, 4)              \
-  X(4, 2, 3, 4, 4, 32, 4)              \
-  X(5, 2, 4, 4, 4, 16, 8)              \
-  X(6, 2, 2, 4, 4, 32, 4)              \
-  X(7, 2, 2, 4, 4, 32, 8)              \
-  X(8, 1, 4, 8, 4, 32, 4)
-hipError_t launch_mac_lds(int variant, const uint64_t* qntt, const uint2* db, int Q, int d, int L,
+  X(1, 2, 4, 4, 4, 32, 4, 2)           \
+  X(2, 2, 4, 4, 4, 32, 4, 1)           \
+  X(3, 2, 3, 4, 4, 32, 4, 2)           \
+  X(4, 2, 3, 4, 4, 32, 4, 1)           \
+  X(5, 2, 2, 4, 4, 32, 4, 2)           \
+  X(6, 1, 4, 8, 4, 32, 4, 2)           \
+  X(7, 2, 4, 4, 4, 32, 8, 1)           \
+  X(8, 2, 3, 4, 4, 32, 8, 1)           \
+  X(9, 2, 4, 2, 4, 32, 4, 1)           \
+  X(10, 2, 4, 4, 2, 32, 4, 1)          \
+  X(11, 2, 3, 2, 4, 32, 4, 1)
+// Direct-to-LDS variants (same parameters), ids 21 and up.
+#define SANNS_MAC_DL_VARIANTS(X)       \
+  X(21, 2, 4, 4, 4, 32, 4, 1)          \
+  X(22, 2, 4, 2, 4, 32, 4, 1)          \
+  X(23, 1, 4, 8, 4, 32, 4, 2)          \
+  X(24, 2, 4, 4, 4, 32, 8, 1)          \
+  X(25, 2, 3, 4, 4, 32, 8, 1)          \
+  X(26, 2, 4, 2, 4, 32, 8, 1)          \
+  X(27, 2, 6, 2, 4, 32, 4, 1)
+hipError_t launch_mac_lds(int variant, const uint2* qntt, const uint2* db, int Q, int d, int L,
                           int logN, int C, const PrimeSet& ps, uint64_t* out, hipStream_t st);
 int mac_lds_min_n(int variant);  // slots per block (N must be a multiple); 0 if unknown
 hipError_t launch_gather(const void* pts, int is_signed, long n, int d,
@@ -55,7 +71,7 @@ hipError_t launch_decrypt(const uint64_t* ct, int M, const uint64_t* sk_ntt,
                           const uint32_t* qnorm2, uint32_t* out, int L, int logN,
                           const PrimeSet& ps, const TwSet& tws, const DecodeConst& D,
                           hipStream_t st);
-hipError_t launch_mult_plain(const uint64_t* cq, const uint2* db, int i, int k, int d, int C,
+hipError_t launch_mult_plain(const uint2* cq, const uint2* db, int i, int k, int d, int C,
                              int L, int logN, const PrimeSet& ps, uint64_t* tmp,
                              hipStream_t st);
 hipError_t launch_add(uint64_t* acc, const uint64_t* tmp, int L, int logN, const PrimeSet& ps,

@@ -93,7 +93,7 @@ int log2u(uint32_t x) {
   return l;
 }
 
-const int kDefaultLdsVariant = 1;  // fastest at 1M x 128, 64 queries
+const int kDefaultLdsVariant = 22;  // fastest at 1M x 128, 64 queries
 
 const int kLogqCap[] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 27, 54, 109, 218, 438, 881};
 
@@ -513,7 +513,7 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
   };
   HIP_TRY(mark(SANNS_PHASE_QUERY_NTT, false));
   HIP_TRY(launch_ntt_fwd(ct_in, qntt, (int)(Q * d * 2 * L), ctx->logN, (int)L, ctx->ps,
-                         ctx->tws, ctx->d_err, st));
+                         ctx->tws, ctx->d_err, 1, st));
   HIP_TRY(mark(SANNS_PHASE_QUERY_NTT, true));
   HIP_TRY(mark(SANNS_PHASE_MASKS, false));
   HIP_TRY(launch_masks(K, qids, dwork, (int)C, (int)M, ctx->logN, (uint32_t)ctx->p.t, ctx->tone,
@@ -521,11 +521,11 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
   HIP_TRY(mark(SANNS_PHASE_MASKS, true));
   HIP_TRY(mark(SANNS_PHASE_MAC, false));
   if (lds > 0)
-    HIP_TRY(launch_mac_lds(lds, qntt, res, (int)Q, (int)d, (int)L, ctx->logN, (int)C, ctx->ps,
-                           ct_out, st));
+    HIP_TRY(launch_mac_lds(lds, (const uint2*)qntt, res, (int)Q, (int)d, (int)L, ctx->logN,
+                           (int)C, ctx->ps, ct_out, st));
   else
-    HIP_TRY(launch_mac(qt, ct, qntt, res, dtiles, n_tiles, (int)Q, (int)d, (int)L, ctx->logN,
-                       (int)C, ctx->ps, ct_out, st));
+    HIP_TRY(launch_mac(qt, ct, (const uint2*)qntt, res, dtiles, n_tiles, (int)Q, (int)d, (int)L,
+                       ctx->logN, (int)C, ctx->ps, ct_out, st));
   HIP_TRY(mark(SANNS_PHASE_MAC, true));
   HIP_TRY(mark(SANNS_PHASE_INTT_MASK, false));
   HIP_TRY(launch_intt_mask(ct_out, share, norms, dwork, (int)C, (int)M, ctx->logN, (int)L,
@@ -550,12 +550,13 @@ sanns_status enqueue_plain(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
   for (uint32_t qi = 0; qi < Q; ++qi)
     for (uint32_t i = 0; i < d; ++i)
       HIP_TRY(launch_ntt_fwd(ct_in + ((size_t)qi * d + i) * ctw, qntt + ((size_t)qi * d + i) * ctw,
-                             (int)(2 * L), ctx->logN, (int)L, ctx->ps, ctx->tws, ctx->d_err, st));
+                             (int)(2 * L), ctx->logN, (int)L, ctx->ps, ctx->tws, ctx->d_err, 1,
+                             st));
   for (uint32_t m = 0; m < M; ++m) {
     const uint32_t qi = hwork[2 * m], k = hwork[2 * m + 1];
     uint64_t* acc = ct_out + (size_t)m * ctw;
     for (uint32_t i = 0; i < d; ++i) {
-      const uint64_t* cq = qntt + ((size_t)qi * d + i) * ctw;
+      const uint2* cq = (const uint2*)(qntt + ((size_t)qi * d + i) * ctw);
       if (i == 0) {
         HIP_TRY(launch_mult_plain(cq, res, (int)i, (int)k, (int)d, (int)C, (int)L, ctx->logN,
                                   ctx->ps, acc, st));
