@@ -24,9 +24,10 @@ struct DecodeConst {
   int words;                           // words used by q and the sums
 };
 
-// Twiddle tables of one limb: [4][N] = psi_rev, psi_rev', ipsi_rev, ipsi_rev'.
+// Twiddle tables of one limb: N (psi_rev, psi_rev') pairs, then N
+// (ipsi_rev, ipsi_rev') pairs whose entry 0 holds ipsi_rev[1] N^-1.
 struct TwSet {
-  const uint64_t* tw[kMaxLimbs];
+  const u64x2* tw[kMaxLimbs];
 };
 
 struct MaskKey {

@@ -17,19 +17,6 @@ namespace sanns {
 // helpers
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ const uint64_t* tw_fwd(const TwSet& T, int l, int N) {
-  return T.tw[l];
-}
-__device__ __forceinline__ const uint64_t* twp_fwd(const TwSet& T, int l, int N) {
-  return T.tw[l] + N;
-}
-__device__ __forceinline__ const uint64_t* tw_inv(const TwSet& T, int l, int N) {
-  return T.tw[l] + 2 * N;
-}
-__device__ __forceinline__ const uint64_t* twp_inv(const TwSet& T, int l, int N) {
-  return T.tw[l] + 3 * N;
-}
-
 // General product of two residues (Karatsuba on 27-bit halves, then the
 // same fold as the multiply-accumulate).
 __device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, const Prime& P) {
@@ -43,28 +30,6 @@ __device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, const Prime& 
   return acc3_reduce(acc, P);
 }
 
-// Move residues held at the last forward pass's positions to the first
-// inverse pass's positions (through LDS).
-__device__ __forceinline__ void remap_fwd_to_inv(uint64_t (&v)[16], uint64_t* lds, int logN,
-                                                 int tid) {
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 16; ++a) lds[lds_pad(fwd_last_index(tid, a, logN))] = v[a];
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 16; ++a) v[a] = lds[lds_pad(inv_first_index(tid, a, logN))];
-}
-
-__device__ __forceinline__ void reduce4q(uint64_t (&v)[16], uint64_t q) {
-#pragma unroll
-  for (int a = 0; a < 16; ++a) v[a] = csub(csub(v[a], 2 * q), q);
-}
-
-__device__ __forceinline__ void scale_ninv(uint64_t (&v)[16], const Prime& P) {
-#pragma unroll
-  for (int a = 0; a < 16; ++a) v[a] = shoup(v[a], P.ninv, P.ninvp, P.q);
-}
-
 // --------------------------------------------------------------------------
 // forward / inverse transforms of independent polynomials
 // --------------------------------------------------------------------------
@@ -72,11 +37,13 @@ __device__ __forceinline__ void scale_ninv(uint64_t (&v)[16], const Prime& P) {
 // One polynomial per workgroup; polynomial p uses limb p % L.  With split
 // set the output residues are stored as their 27-bit halves (uint2), the
 // form the multiply-accumulate kernels consume.
-__global__ void __launch_bounds__(1024)
-k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int logN, int L,
-          PrimeSet ps, TwSet tws, uint32_t* err, int split) {
+template <int LOGN>
+__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
+k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int L, PrimeSet ps,
+          TwSet tws, uint32_t* err, int split) {
   extern __shared__ uint64_t lds[];
-  const int tid = threadIdx.x, N = 1 << logN;
+  constexpr int N = NttShape<LOGN>::N;
+  const int tid = threadIdx.x;
   const int p = blockIdx.x, l = p % L;
   const Prime& P = ps.p[l];
   const uint64_t* src = in + (size_t)p * N;
@@ -84,12 +51,11 @@ k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int logN,
   bool bad = false;
 #pragma unroll
   for (int a = 0; a < 16; ++a) {
-    v[a] = src[fwd_first_index(tid, a, logN)];
+    v[a] = src[coef_index<LOGN>(tid, a)];
     bad |= v[a] >= P.q;
   }
   if (bad && err) atomicOr(err, 1u);
-  ntt_fwd(v, lds, logN, tid, tw_fwd(tws, l, N), twp_fwd(tws, l, N), P.q);
-  reduce4q(v, P.q);
+  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P.q);
   uint64_t* dst = out + (size_t)p * N;
   if (split) {
     uint2* dst2 = reinterpret_cast<uint2*>(dst);
@@ -97,30 +63,31 @@ k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int logN,
     for (int a = 0; a < 16; ++a) {
       uint2 y;
       split27(v[a], y.x, y.y);
-      dst2[fwd_last_index(tid, a, logN)] = y;
+      dst2[ntt_slot<LOGN>(tid, a)] = y;
     }
   } else {
 #pragma unroll
-    for (int a = 0; a < 16; ++a) dst[fwd_last_index(tid, a, logN)] = v[a];
+    for (int a = 0; a < 16; ++a) dst[ntt_slot<LOGN>(tid, a)] = v[a];
   }
 }
 
 // In-place inverse transform, result multiplied by N^-1 and in [0, q).
-__global__ void __launch_bounds__(1024)
-k_ntt_inv(uint64_t* __restrict__ io, int logN, int L, PrimeSet ps, TwSet tws) {
+template <int LOGN>
+__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
+k_ntt_inv(uint64_t* __restrict__ io, int L, PrimeSet ps, TwSet tws) {
   extern __shared__ uint64_t lds[];
-  const int tid = threadIdx.x, N = 1 << logN;
+  constexpr int N = NttShape<LOGN>::N;
+  const int tid = threadIdx.x;
   const int p = blockIdx.x, l = p % L;
   const Prime& P = ps.p[l];
   uint64_t* buf = io + (size_t)p * N;
   uint64_t v[16];
 #pragma unroll
-  for (int a = 0; a < 16; ++a) v[a] = buf[inv_first_index(tid, a, logN)];
-  ntt_inv(v, lds, logN, tid, tw_inv(tws, l, N), twp_inv(tws, l, N), P.q);
-  scale_ninv(v, P);
+  for (int a = 0; a < 16; ++a) v[a] = buf[ntt_slot<LOGN>(tid, a)];
+  ntt_inv<LOGN>(v, lds, tid, tws.tw[l] + N, P);
   __syncthreads();  // every thread has read its inputs before any overwrite
 #pragma unroll
-  for (int a = 0; a < 16; ++a) buf[inv_last_index(tid, a, logN)] = v[a];
+  for (int a = 0; a < 16; ++a) buf[coef_index<LOGN>(tid, a)] = v[a];
 }
 
 // --------------------------------------------------------------------------
@@ -205,20 +172,21 @@ k_masks(MaskKey K, const uint64_t* __restrict__ qids, const uint32_t* __restrict
 
 // Polynomial p = (m 2 + c) L + l of ct_out: INTT, times N^-1, and for c = 0
 // add Delta_l [norm - r]_t at every coefficient.
-__global__ void __launch_bounds__(1024)
+template <int LOGN>
+__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
 k_intt_mask(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
             const uint32_t* __restrict__ norms, const uint32_t* __restrict__ work, int C,
-            int logN, int L, uint32_t t, PrimeSet ps, TwSet tws) {
+            int L, uint32_t t, PrimeSet ps, TwSet tws) {
   extern __shared__ uint64_t lds[];
-  const int tid = threadIdx.x, N = 1 << logN;
+  constexpr int N = NttShape<LOGN>::N;
+  const int tid = threadIdx.x;
   const int p = blockIdx.x, l = p % L, c = (p / L) & 1, m = p / (2 * L);
   const Prime& P = ps.p[l];
   uint64_t* buf = ct + (size_t)p * N;
   uint64_t v[16];
 #pragma unroll
-  for (int a = 0; a < 16; ++a) v[a] = buf[inv_first_index(tid, a, logN)];
-  ntt_inv(v, lds, logN, tid, tw_inv(tws, l, N), twp_inv(tws, l, N), P.q);
-  scale_ninv(v, P);
+  for (int a = 0; a < 16; ++a) v[a] = buf[ntt_slot<LOGN>(tid, a)];
+  ntt_inv<LOGN>(v, lds, tid, tws.tw[l] + N, P);
   if (c == 0) {
     int qi, k;
     work_pair(work, m, C, qi, k);
@@ -226,7 +194,7 @@ k_intt_mask(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
     const uint32_t* r = share + (size_t)m * N;
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
-      const int j = inv_last_index(tid, a, logN);
+      const int j = coef_index<LOGN>(tid, a);
       const uint32_t pn = nrm[j], rj = r[j];
       const uint64_t mv = pn >= rj ? pn - rj : pn + t - rj;
       v[a] = addmod(v[a], shoup(mv, P.delta, P.deltap, P.q), P.q);
@@ -234,7 +202,7 @@ k_intt_mask(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
   }
   __syncthreads();
 #pragma unroll
-  for (int a = 0; a < 16; ++a) buf[inv_last_index(tid, a, logN)] = v[a];
+  for (int a = 0; a < 16; ++a) buf[coef_index<LOGN>(tid, a)] = v[a];
 }
 
 // --------------------------------------------------------------------------
@@ -765,11 +733,13 @@ k_gather(const uint8_t* __restrict__ pts, int is_signed, long n, int d,
 
 // Workgroup per (l, k, i) with k in [k0, k0 + nk): lift the signed
 // plaintext row mod q_l, forward NTT, store as 27-bit halves.
-__global__ void __launch_bounds__(1024)
+template <int LOGN>
+__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
 k_encode_ntt(const int16_t* __restrict__ gt, uint2* __restrict__ dbres, int k0, int nk, int C,
-             int d, int logN, int L, PrimeSet ps, TwSet tws) {
+             int d, int L, PrimeSet ps, TwSet tws) {
   extern __shared__ uint64_t lds[];
-  const int tid = threadIdx.x, N = 1 << logN;
+  constexpr int N = NttShape<LOGN>::N;
+  const int tid = threadIdx.x;
   const long bl = blockIdx.x;  // (l nk + k - k0) d + i
   const int l = (int)(bl / ((long)nk * d));
   const long ki = bl % ((long)nk * d);
@@ -779,17 +749,16 @@ k_encode_ntt(const int16_t* __restrict__ gt, uint2* __restrict__ dbres, int k0, 
   uint64_t v[16];
 #pragma unroll
   for (int a = 0; a < 16; ++a) {
-    const int x = src[fwd_first_index(tid, a, logN)];
+    const int x = src[coef_index<LOGN>(tid, a)];
     v[a] = x < 0 ? P.q - (uint64_t)(-x) : (uint64_t)x;
   }
-  ntt_fwd(v, lds, logN, tid, tw_fwd(tws, l, N), twp_fwd(tws, l, N), P.q);
-  reduce4q(v, P.q);
+  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P.q);
   uint2* dst = dbres + (size_t)b * N;
 #pragma unroll
   for (int a = 0; a < 16; ++a) {
     uint2 y;
     split27(v[a], y.x, y.y);
-    dst[fwd_last_index(tid, a, logN)] = y;
+    dst[ntt_slot<LOGN>(tid, a)] = y;
   }
 }
 
@@ -798,31 +767,33 @@ k_encode_ntt(const int16_t* __restrict__ gt, uint2* __restrict__ dbres, int k0, 
 // --------------------------------------------------------------------------
 
 // Workgroup per limb: NTT of the ternary secret lifted mod q_l.
-__global__ void __launch_bounds__(1024)
-k_sk_ntt(const int8_t* __restrict__ sk, uint64_t* __restrict__ out, int logN, PrimeSet ps,
-         TwSet tws) {
+template <int LOGN>
+__global__ void __launch_bounds__(NttShape<LOGN>::T)
+k_sk_ntt(const int8_t* __restrict__ sk, uint64_t* __restrict__ out, PrimeSet ps, TwSet tws) {
   extern __shared__ uint64_t lds[];
-  const int tid = threadIdx.x, N = 1 << logN, l = blockIdx.x;
+  constexpr int N = NttShape<LOGN>::N;
+  const int tid = threadIdx.x, l = blockIdx.x;
   const Prime& P = ps.p[l];
   uint64_t v[16];
 #pragma unroll
   for (int a = 0; a < 16; ++a) {
-    const int x = sk[fwd_first_index(tid, a, logN)];
+    const int x = sk[coef_index<LOGN>(tid, a)];
     v[a] = x < 0 ? P.q - (uint64_t)(-x) : (uint64_t)x;
   }
-  ntt_fwd(v, lds, logN, tid, tw_fwd(tws, l, N), twp_fwd(tws, l, N), P.q);
-  reduce4q(v, P.q);
+  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P.q);
 #pragma unroll
-  for (int a = 0; a < 16; ++a) out[(size_t)l * N + fwd_last_index(tid, a, logN)] = v[a];
+  for (int a = 0; a < 16; ++a) out[(size_t)l * N + ntt_slot<LOGN>(tid, a)] = v[a];
 }
 
 // Workgroup per (query, coordinate, limb): c1 = a, c0 = -a s + e + Delta m.
-__global__ void __launch_bounds__(1024)
+template <int LOGN>
+__global__ void __launch_bounds__(NttShape<LOGN>::T)
 k_encrypt(const uint64_t* __restrict__ a_in, const int16_t* __restrict__ e_in,
           const int32_t* __restrict__ msgs, const uint64_t* __restrict__ sk_ntt,
-          uint64_t* __restrict__ ct, int L, int logN, uint32_t t, PrimeSet ps, TwSet tws) {
+          uint64_t* __restrict__ ct, int L, uint32_t t, PrimeSet ps, TwSet tws) {
   extern __shared__ uint64_t lds[];
-  const int tid = threadIdx.x, N = 1 << logN;
+  constexpr int N = NttShape<LOGN>::N;
+  const int tid = threadIdx.x;
   const int b = blockIdx.x;  // (qi d + i) L + l
   const int l = b % L;
   const int qd = b / L;      // qi d + i
@@ -830,15 +801,12 @@ k_encrypt(const uint64_t* __restrict__ a_in, const int16_t* __restrict__ e_in,
   const uint64_t* a = a_in + (size_t)b * N;
   uint64_t v[16];
 #pragma unroll
-  for (int x = 0; x < 16; ++x) v[x] = a[fwd_first_index(tid, x, logN)];
-  ntt_fwd(v, lds, logN, tid, tw_fwd(tws, l, N), twp_fwd(tws, l, N), P.q);
-  reduce4q(v, P.q);
+  for (int x = 0; x < 16; ++x) v[x] = a[coef_index<LOGN>(tid, x)];
+  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P.q);
 #pragma unroll
   for (int x = 0; x < 16; ++x)
-    v[x] = mulmod(v[x], sk_ntt[(size_t)l * N + fwd_last_index(tid, x, logN)], P);
-  remap_fwd_to_inv(v, lds, logN, tid);
-  ntt_inv(v, lds, logN, tid, tw_inv(tws, l, N), twp_inv(tws, l, N), P.q);
-  scale_ninv(v, P);
+    v[x] = mulmod(v[x], sk_ntt[(size_t)l * N + ntt_slot<LOGN>(tid, x)], P);
+  ntt_inv<LOGN>(v, lds, tid, tws.tw[l] + N, P);
   // message [m]_t as a constant: Delta m in coefficient 0
   const int64_t mraw = msgs[qd];
   int64_t mm = mraw % (int64_t)t;
@@ -849,7 +817,7 @@ k_encrypt(const uint64_t* __restrict__ a_in, const int16_t* __restrict__ e_in,
   uint64_t* c1 = ct + (((size_t)qd * 2 + 1) * L + l) * N;
 #pragma unroll
   for (int x = 0; x < 16; ++x) {
-    const int j = inv_last_index(tid, x, logN);
+    const int j = coef_index<LOGN>(tid, x);
     const int ej = e[j];
     const uint64_t ev = ej < 0 ? P.q - (uint64_t)(-ej) : (uint64_t)ej;
     uint64_t r = submod(ev, v[x], P.q);
@@ -937,12 +905,14 @@ __device__ __forceinline__ uint32_t crt_round(const uint64_t* xl, int L, const P
 
 // Workgroup per ciphertext: x_l = INTT(NTT(c1) NTT(s)) + c0 per limb, then the
 // exact decode and the client share [m + ||q||^2]_t.
-__global__ void __launch_bounds__(1024)
+template <int LOGN>
+__global__ void __launch_bounds__(NttShape<LOGN>::T)
 k_decrypt(const uint64_t* __restrict__ ct, const uint64_t* __restrict__ sk_ntt,
-          const uint32_t* __restrict__ qnorm2, uint32_t* __restrict__ outp, int L, int logN,
+          const uint32_t* __restrict__ qnorm2, uint32_t* __restrict__ outp, int L,
           PrimeSet ps, TwSet tws, DecodeConst D) {
   extern __shared__ uint64_t lds[];
-  const int tid = threadIdx.x, N = 1 << logN, m = blockIdx.x;
+  constexpr int N = NttShape<LOGN>::N;
+  const int tid = threadIdx.x, m = blockIdx.x;
   uint64_t x[kMaxLimbs][16];
   for (int l = 0; l < L; ++l) {
     const Prime& P = ps.p[l];
@@ -950,18 +920,15 @@ k_decrypt(const uint64_t* __restrict__ ct, const uint64_t* __restrict__ sk_ntt,
     const uint64_t* c1 = ct + (((size_t)m * 2 + 1) * L + l) * N;
     uint64_t v[16];
 #pragma unroll
-    for (int a = 0; a < 16; ++a) v[a] = c1[fwd_first_index(tid, a, logN)];
-    ntt_fwd(v, lds, logN, tid, tw_fwd(tws, l, N), twp_fwd(tws, l, N), P.q);
-    reduce4q(v, P.q);
+    for (int a = 0; a < 16; ++a) v[a] = c1[coef_index<LOGN>(tid, a)];
+    ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P.q);
 #pragma unroll
     for (int a = 0; a < 16; ++a)
-      v[a] = mulmod(v[a], sk_ntt[(size_t)l * N + fwd_last_index(tid, a, logN)], P);
-    remap_fwd_to_inv(v, lds, logN, tid);
-    ntt_inv(v, lds, logN, tid, tw_inv(tws, l, N), twp_inv(tws, l, N), P.q);
-    scale_ninv(v, P);
+      v[a] = mulmod(v[a], sk_ntt[(size_t)l * N + ntt_slot<LOGN>(tid, a)], P);
+    ntt_inv<LOGN>(v, lds, tid, tws.tw[l] + N, P);
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
-      const uint64_t r = addmod(v[a], c0[inv_last_index(tid, a, logN)], P.q);
+      const uint64_t r = addmod(v[a], c0[coef_index<LOGN>(tid, a)], P.q);
 #pragma unroll
       for (int ll = 0; ll < kMaxLimbs; ++ll)
         if (ll == l) x[ll][a] = r;
@@ -975,7 +942,7 @@ k_decrypt(const uint64_t* __restrict__ ct, const uint64_t* __restrict__ sk_ntt,
     for (int l = 0; l < kMaxLimbs; ++l) xl[l] = x[l][a];
     const uint32_t mm = crt_round(xl, L, ps, D);
     const uint64_t s = (uint64_t)mm + qn;
-    outp[(size_t)m * N + inv_last_index(tid, a, logN)] = (uint32_t)(s >= D.t ? s - D.t : s);
+    outp[(size_t)m * N + coef_index<LOGN>(tid, a)] = (uint32_t)(s >= D.t ? s - D.t : s);
   }
 }
 
@@ -1028,25 +995,46 @@ k_add_plain(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
 // host launchers
 // --------------------------------------------------------------------------
 
-static inline size_t ntt_lds_bytes(int logN) {
-  const int N = 1 << logN;
-  return (size_t)(N + (N >> 4) + 1) * sizeof(uint64_t);
+// Transform-size dispatch: every kernel built on the register NTT is
+// instantiated for log2 N = 4 .. 14.
+#define SANNS_LOGN_CASES(X) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14)
+
+template <int LG, typename K, typename... A>
+static void ntt_launch(K kern, unsigned grid, hipStream_t st, A... args) {
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NttShape<LG>::T), NttShape<LG>::lds_bytes, st,
+                     args...);
 }
 
 hipError_t launch_ntt_fwd(const uint64_t* in, uint64_t* out, int n_polys, int logN, int L,
                           const PrimeSet& ps, const TwSet& tws, uint32_t* err, int split,
                           hipStream_t st) {
   if (n_polys <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ntt_fwd, dim3(n_polys), dim3(1 << (logN - 4)), ntt_lds_bytes(logN),
-                     st, in, out, logN, L, ps, tws, err, split);
+  switch (logN) {
+#define SANNS_CASE(LG)                                                                   \
+  case LG:                                                                               \
+    ntt_launch<LG>(k_ntt_fwd<LG>, (unsigned)n_polys, st, in, out, L, ps, tws, err, split); \
+    break;
+    SANNS_LOGN_CASES(SANNS_CASE)
+#undef SANNS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_ntt_inv(uint64_t* io, int n_polys, int logN, int L, const PrimeSet& ps,
                           const TwSet& tws, hipStream_t st) {
   if (n_polys <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_ntt_inv, dim3(n_polys), dim3(1 << (logN - 4)), ntt_lds_bytes(logN),
-                     st, io, logN, L, ps, tws);
+  switch (logN) {
+#define SANNS_CASE(LG)                                                 \
+  case LG:                                                             \
+    ntt_launch<LG>(k_ntt_inv<LG>, (unsigned)n_polys, st, io, L, ps, tws); \
+    break;
+    SANNS_LOGN_CASES(SANNS_CASE)
+#undef SANNS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1064,9 +1052,17 @@ hipError_t launch_intt_mask(uint64_t* ct, const uint32_t* share, const uint32_t*
                             const uint32_t* work, int C, int M, int logN, int L, uint32_t t,
                             const PrimeSet& ps, const TwSet& tws, hipStream_t st) {
   if (M <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_intt_mask, dim3(M * 2 * L), dim3(1 << (logN - 4)),
-                     ntt_lds_bytes(logN), st, ct, share, norms, work, C, logN, L, t, ps,
-                     tws);
+  switch (logN) {
+#define SANNS_CASE(LG)                                                                  \
+  case LG:                                                                              \
+    ntt_launch<LG>(k_intt_mask<LG>, (unsigned)(M * 2 * L), st, ct, share, norms, work, C, \
+                   L, t, ps, tws);                                                      \
+    break;
+    SANNS_LOGN_CASES(SANNS_CASE)
+#undef SANNS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1183,23 +1179,51 @@ hipError_t launch_gather(const void* pts, int is_signed, long n, int d,
 hipError_t launch_encode_ntt(const int16_t* gt, uint2* dbres, int k0, int nk, int C, int d,
                              int logN, int L, const PrimeSet& ps, const TwSet& tws,
                              hipStream_t st) {
-  hipLaunchKernelGGL(k_encode_ntt, dim3((unsigned)((long)L * nk * d)), dim3(1 << (logN - 4)),
-                     ntt_lds_bytes(logN), st, gt, dbres, k0, nk, C, d, logN, L, ps, tws);
+  const unsigned grid = (unsigned)((long)L * nk * d);
+  if (grid == 0) return hipSuccess;
+  switch (logN) {
+#define SANNS_CASE(LG)                                                                \
+  case LG:                                                                            \
+    ntt_launch<LG>(k_encode_ntt<LG>, grid, st, gt, dbres, k0, nk, C, d, L, ps, tws);   \
+    break;
+    SANNS_LOGN_CASES(SANNS_CASE)
+#undef SANNS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_sk_ntt(const int8_t* sk, uint64_t* out, int logN, int L, const PrimeSet& ps,
                          const TwSet& tws, hipStream_t st) {
-  hipLaunchKernelGGL(k_sk_ntt, dim3(L), dim3(1 << (logN - 4)), ntt_lds_bytes(logN), st, sk,
-                     out, logN, ps, tws);
+  switch (logN) {
+#define SANNS_CASE(LG)                                                   \
+  case LG:                                                               \
+    ntt_launch<LG>(k_sk_ntt<LG>, (unsigned)L, st, sk, out, ps, tws);     \
+    break;
+    SANNS_LOGN_CASES(SANNS_CASE)
+#undef SANNS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_encrypt(const uint64_t* a, const int16_t* e, const int32_t* msgs,
                           const uint64_t* sk_ntt, uint64_t* ct, int Qd, int L, int logN,
                           uint32_t t, const PrimeSet& ps, const TwSet& tws, hipStream_t st) {
-  hipLaunchKernelGGL(k_encrypt, dim3(Qd * L), dim3(1 << (logN - 4)), ntt_lds_bytes(logN), st,
-                     a, e, msgs, sk_ntt, ct, L, logN, t, ps, tws);
+  if (Qd <= 0) return hipSuccess;
+  switch (logN) {
+#define SANNS_CASE(LG)                                                                 \
+  case LG:                                                                             \
+    ntt_launch<LG>(k_encrypt<LG>, (unsigned)(Qd * L), st, a, e, msgs, sk_ntt, ct, L, t, \
+                   ps, tws);                                                           \
+    break;
+    SANNS_LOGN_CASES(SANNS_CASE)
+#undef SANNS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1207,8 +1231,17 @@ hipError_t launch_decrypt(const uint64_t* ct, int M, const uint64_t* sk_ntt,
                           const uint32_t* qnorm2, uint32_t* out, int L, int logN,
                           const PrimeSet& ps, const TwSet& tws, const DecodeConst& D,
                           hipStream_t st) {
-  hipLaunchKernelGGL(k_decrypt, dim3(M), dim3(1 << (logN - 4)), ntt_lds_bytes(logN), st, ct,
-                     sk_ntt, qnorm2, out, L, logN, ps, tws, D);
+  if (M <= 0) return hipSuccess;
+  switch (logN) {
+#define SANNS_CASE(LG)                                                                   \
+  case LG:                                                                               \
+    ntt_launch<LG>(k_decrypt<LG>, (unsigned)M, st, ct, sk_ntt, qnorm2, out, L, ps, tws, D); \
+    break;
+    SANNS_LOGN_CASES(SANNS_CASE)
+#undef SANNS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -13,6 +13,8 @@
 
 namespace sanns {
 
+typedef HIP_vector_type<unsigned long long, 2> u64x2;  // (w, Shoup companion)
+
 __device__ __forceinline__ uint32_t lo32(uint64_t x) { return (uint32_t)x; }
 __device__ __forceinline__ uint32_t hi32(uint64_t x) { return (uint32_t)(x >> 32); }
 
@@ -44,7 +46,34 @@ __device__ __forceinline__ uint64_t shoup_lazy(uint64_t x, uint64_t w, uint64_t 
 }
 
 __device__ __forceinline__ uint64_t csub(uint64_t x, uint64_t q) {
-  return x >= q ? x - q : x;
+  // x - q with the borrow chain's final borrow selecting the result
+  unsigned b0, b1;
+  const uint32_t lo = __builtin_subc(lo32(x), lo32(q), 0u, &b0);
+  const uint32_t hi = __builtin_subc(hi32(x), hi32(q), b0, &b1);
+  return b1 ? x : (((uint64_t)hi << 32) | lo);
+}
+
+// The 32-bit halves of a value, hidden from the optimiser so that products
+// spelled out below in 32-bit pieces stay as written instead of being folded
+// back into a generic 64-bit multiply (an empty asm statement, no code).
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+  asm("" : "+v"(x));
+  return x;
+}
+
+// Shoup product with the quotient estimated from three of the four 32-bit
+// partial products of x w' (x0 p0 and the low halves of x1 p0 and x0 p1 are
+// dropped, which lowers the estimate by at most 2), and x w - Qhat q formed
+// as x w + Qhat nq with nq = 2^64 - q.  Result in [0, 4q) for x < 2^62.
+__device__ __forceinline__ uint64_t shoup_approx(uint64_t x, uint64_t w, uint64_t wp,
+                                                 uint64_t nq) {
+  const uint32_t x0 = opaque(lo32(x)), x1 = opaque(hi32(x));
+  const uint32_t p0 = lo32(wp), p1 = hi32(wp);
+  const uint64_t qh = mul32x32(x1, p1) + __umulhi(x1, p0) + __umulhi(x0, p1);
+  const uint32_t q0 = opaque(lo32(qh)), q1 = opaque(hi32(qh));
+  const uint64_t lo = mul32x32(x0, lo32(w)) + mul32x32(q0, lo32(nq));
+  const uint32_t hi = hi32(lo) + x0 * hi32(w) + x1 * lo32(w) + q0 * hi32(nq) + q1 * lo32(nq);
+  return ((uint64_t)hi << 32) | lo32(lo);
 }
 
 // Shoup product reduced to [0, q).

@@ -1,214 +1,213 @@
 // Negacyclic number-theoretic transform over Z_q[x]/(x^N + 1) for one
-// polynomial per workgroup, N = 16 T residues held 16 per thread.
+// polynomial per workgroup, N = 16 T residues held 16 per thread, with the
+// transform size a compile-time parameter so that every index below folds
+// to a per-thread base plus a constant.
 //
 // Forward: merged-psi Cooley-Tukey (bit-reversed output), the butterfly at
 // stride 2^p between indices j and j + 2^p uses Psi_rev[(N + j) >> (p + 1)],
 // Psi_rev[m] = psi^bitrev(m) with psi a primitive 2N-th root of unity mod q.
-// Inverse: Gentleman-Sande with Psi^-1 tables, then multiplication by N^-1.
-// Lazy reduction (Harvey): forward values stay in [0, 4q), inverse in [0, 2q).
+// Inverse: Gentleman-Sande with the Psi^-1 tables; its last stage also
+// multiplies by N^-1 (entry 0 of the inverse table, never a stage twiddle,
+// holds Psi^-1_rev[1] N^-1).
+// Lazy reduction (Harvey) with the estimated Shoup quotient (products in
+// [0, 4q)): forward values stay in [0, 8q), inverse values in [0, 4q).
 //
-// Stages are grouped in passes of up to four index bits.  In a pass that
-// covers bits [lo, lo + B) a thread holds the 16 residues whose index has
-// its thread id (and, when B < 4, 4 - B extra bits from the register slot)
-// in the other bit positions; the B stages of the pass run in registers and
-// passes exchange data through LDS, padded by one word per 16 so that the
-// strided patterns do not collide on banks.
+// Stages are grouped in passes of up to four index bits; the narrow pass (if
+// log2 N is not a multiple of four) is the forward's first and the inverse's
+// last, so both transforms meet at a pass over bits [0, 4).  In a pass over
+// bits [lo, lo + B) a thread holds the 16 residues whose index has its thread
+// id (and, when B < 4, 4 - B extra bits from the register slot) in the other
+// bit positions; the B stages run in registers and passes exchange data
+// through LDS, padded by one word per 16 against bank collisions.
+//
+// Global layouts that follow:
+//   coefficient form: slot a of thread tid holds coefficient coef_index(tid, a),
+//     consecutive threads reading consecutive words;
+//   NTT form: slot a of thread tid holds the bit-reversed evaluation
+//     a + 16 tid, stored at word ntt_slot(tid, a) = a T + tid, again
+//     consecutive across threads.  Every consumer of NTT-form vectors works
+//     slot-wise, so this storage order is private to the library.
 #pragma once
 #include "modarith.h"
 
 namespace sanns {
 
-__device__ __forceinline__ int lds_pad(int idx) { return idx + (idx >> 4); }
+template <int LOGN>
+struct NttShape {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int T = N >> 4;                 // threads per transform
+  static constexpr int P = (LOGN + 3) >> 2;        // passes
+  static constexpr int R = LOGN - 4 * (P - 1);     // bits of the narrow pass
+  static constexpr int fwd_lo(int j) { return j == 0 ? LOGN - R : LOGN - R - 4 * j; }
+  static constexpr int fwd_b(int j) { return j == 0 ? R : 4; }
+  static constexpr int inv_lo(int j) { return 4 * j; }
+  static constexpr int inv_b(int j) { return j == P - 1 ? R : 4; }
+  static constexpr size_t lds_bytes = (size_t)(N + (N >> 4)) * sizeof(uint64_t);
+};
 
-// Index of register slot a (0..15) of thread tid in a pass covering bits
-// [lo, lo + B) of a 2^logN-point transform.
-template <int B>
-__device__ __forceinline__ int elem_index(int tid, int a, int lo, int logN) {
-  const int r = (B == 4) ? tid : (tid | ((a >> B) << (logN - 4)));
+__device__ __forceinline__ constexpr int lds_pad(int idx) { return idx + (idx >> 4); }
+
+// Index of register slot a (0..15) of thread tid in a pass over bits
+// [LO, LO + B).  The thread's bits and the slot's bits land in disjoint
+// positions, so eidx(tid, a) = eidx(tid, 0) + eidx(0, a), and the same holds
+// after lds_pad or a right shift: addresses are a base plus a constant.
+template <int LOGN, int B, int LO>
+__device__ __forceinline__ constexpr int eidx(int tid, int a) {
+  const int r = (B == 4) ? tid : (tid | ((a >> B) << (LOGN - 4)));
   const int pb = a & ((1 << B) - 1);
-  return (r & ((1 << lo) - 1)) | (pb << lo) | ((r >> lo) << (lo + B));
+  return (r & ((1 << LO) - 1)) | (pb << LO) | ((r >> LO) << (LO + B));
 }
 
-template <int B>
-__device__ __forceinline__ void fwd_pass(uint64_t (&v)[16], int lo, int logN, int tid,
-                                         const uint64_t* __restrict__ tw,
-                                         const uint64_t* __restrict__ twp, uint64_t q) {
-  const uint64_t q2 = 2 * q;
-  const int N = 1 << logN;
+template <int LOGN>
+__device__ __forceinline__ int coef_index(int tid, int a) {
+  using S = NttShape<LOGN>;
+  return eidx<LOGN, S::R, LOGN - S::R>(tid, a);
+}
+
+template <int LOGN>
+__device__ __forceinline__ int ntt_slot(int tid, int a) {
+  return a * NttShape<LOGN>::T + tid;
+}
+
+// Twiddles of one stage (p1 = p + 1): (N + eidx(tid, a0)) >> p1 is
+// ((N + eidx(tid, 0)) >> p1) + (eidx(0, a0) >> p1).  When every lane bit of
+// the thread id sits below bit LO the base is the same across the wavefront.
+template <int LOGN, int B, int LO>
+__device__ __forceinline__ const u64x2* tw_stage(const u64x2* tw, int tid, int p1) {
+  int b = (NttShape<LOGN>::N + eidx<LOGN, B, LO>(tid, 0)) >> p1;
+  if (LO >= 6) b = __builtin_amdgcn_readfirstlane(b);
+  return tw + b;
+}
+
+template <int LOGN, int B, int LO, bool FIRST>
+__device__ __forceinline__ void fwd_pass(uint64_t (&v)[16], int tid,
+                                         const u64x2* __restrict__ tw, uint64_t q) {
+  const uint64_t q4 = 4 * q, nq = 0 - q;
 #pragma unroll
   for (int rp = B - 1; rp >= 0; --rp) {
-    const int p = lo + rp;
+    const int p = LO + rp;
+    const u64x2* tb = tw_stage<LOGN, B, LO>(tw, tid, p + 1);
 #pragma unroll
     for (int e = 0; e < (16 >> B); ++e) {
 #pragma unroll
       for (int g = 0; g < (1 << (B - 1 - rp)); ++g) {
         const int a0 = (e << B) | (g << (rp + 1));
-        const int w = (N + elem_index<B>(tid, a0, lo, logN)) >> (p + 1);
-        const uint64_t W = tw[w], Wp = twp[w];
+        const u64x2 W = tb[eidx<LOGN, B, LO>(0, a0) >> (p + 1)];
 #pragma unroll
         for (int l = 0; l < (1 << rp); ++l) {
           const int a = a0 | l, b = a | (1 << rp);
           uint64_t X = v[a];
-          X = X >= q2 ? X - q2 : X;
-          const uint64_t T = shoup_lazy(v[b], W, Wp, q);
-          v[a] = X + T;
-          v[b] = X - T + q2;
+          // inputs of the very first stage are already below q
+          if (!(FIRST && rp == B - 1)) X = csub(X, q4);
+          const uint64_t Tm = shoup_approx(v[b], W.x, W.y, nq);
+          v[a] = X + Tm;
+          v[b] = (X + q4) - Tm;
         }
       }
     }
   }
 }
 
-template <int B>
-__device__ __forceinline__ void inv_pass(uint64_t (&v)[16], int lo, int logN, int tid,
-                                         const uint64_t* __restrict__ tw,
-                                         const uint64_t* __restrict__ twp, uint64_t q) {
-  const uint64_t q2 = 2 * q;
-  const int N = 1 << logN;
+template <int LOGN, int B, int LO, bool FIRST, bool LAST>
+__device__ __forceinline__ void inv_pass(uint64_t (&v)[16], int tid,
+                                         const u64x2* __restrict__ tw, const Prime& P) {
+  const uint64_t q4 = 4 * P.q, nq = 0 - P.q;
 #pragma unroll
   for (int rp = 0; rp < B; ++rp) {
-    const int p = lo + rp;
+    const int p = LO + rp;
+    const bool merged = LAST && rp == B - 1;  // the stage that also scales by N^-1
+    const u64x2* tb = tw_stage<LOGN, B, LO>(tw, tid, p + 1);
 #pragma unroll
     for (int e = 0; e < (16 >> B); ++e) {
 #pragma unroll
       for (int g = 0; g < (1 << (B - 1 - rp)); ++g) {
         const int a0 = (e << B) | (g << (rp + 1));
-        const int w = (N + elem_index<B>(tid, a0, lo, logN)) >> (p + 1);
-        const uint64_t W = tw[w], Wp = twp[w];
+        const u64x2 W = merged ? tw[0] : tb[eidx<LOGN, B, LO>(0, a0) >> (p + 1)];
 #pragma unroll
         for (int l = 0; l < (1 << rp); ++l) {
           const int a = a0 | l, b = a | (1 << rp);
           const uint64_t X = v[a], Y = v[b];
           uint64_t s = X + Y;
-          s = s >= q2 ? s - q2 : s;
+          if (merged) {
+            s = shoup_approx(s, P.ninv, P.ninvp, nq);
+          } else if (!(FIRST && rp == 0)) {
+            s = csub(s, q4);  // first-stage inputs are below q, their sum below 2q
+          }
           v[a] = s;
-          v[b] = shoup_lazy(X - Y + q2, W, Wp, q);
+          v[b] = shoup_approx((X + q4) - Y, W.x, W.y, nq);
         }
       }
     }
   }
 }
 
-template <int B>
-__device__ __forceinline__ void lds_store(const uint64_t (&v)[16], uint64_t* lds, int lo,
-                                          int logN, int tid) {
+template <int LOGN, int B, int LO>
+__device__ __forceinline__ void lds_store(const uint64_t (&v)[16], uint64_t* lds, int tid) {
+  uint64_t* base = lds + lds_pad(eidx<LOGN, B, LO>(tid, 0));
 #pragma unroll
-  for (int a = 0; a < 16; ++a) lds[lds_pad(elem_index<B>(tid, a, lo, logN))] = v[a];
+  for (int a = 0; a < 16; ++a) base[lds_pad(eidx<LOGN, B, LO>(0, a))] = v[a];
 }
 
-template <int B>
-__device__ __forceinline__ void lds_load(uint64_t (&v)[16], const uint64_t* lds, int lo,
-                                         int logN, int tid) {
+template <int LOGN, int B, int LO>
+__device__ __forceinline__ void lds_load(uint64_t (&v)[16], const uint64_t* lds, int tid) {
+  const uint64_t* base = lds + lds_pad(eidx<LOGN, B, LO>(tid, 0));
 #pragma unroll
-  for (int a = 0; a < 16; ++a) v[a] = lds[lds_pad(elem_index<B>(tid, a, lo, logN))];
+  for (int a = 0; a < 16; ++a) v[a] = base[lds_pad(eidx<LOGN, B, LO>(0, a))];
 }
 
-// Geometry of pass j.  Forward passes walk the bits from the top, inverse
-// passes from the bottom; only the last pass of either may be narrower.
-__device__ __forceinline__ void fwd_geom(int j, int logN, int& lo, int& b) {
-  const int hi = logN - 4 * j;
-  lo = hi - 4 < 0 ? 0 : hi - 4;
-  b = hi - lo;
-}
-__device__ __forceinline__ void inv_geom(int j, int logN, int& lo, int& b) {
-  lo = 4 * j;
-  b = logN - lo < 4 ? logN - lo : 4;
-}
-__device__ __forceinline__ int n_passes(int logN) { return (logN + 3) >> 2; }
-
-// Global-memory index of register slot a for the first or last pass.
-__device__ __forceinline__ int fwd_first_index(int tid, int a, int logN) {
-  return elem_index<4>(tid, a, logN - 4, logN);
-}
-__device__ __forceinline__ int fwd_last_index(int tid, int a, int logN) {
-  int lo, b;
-  fwd_geom(n_passes(logN) - 1, logN, lo, b);
-  switch (b) {
-    case 1: return elem_index<1>(tid, a, lo, logN);
-    case 2: return elem_index<2>(tid, a, lo, logN);
-    case 3: return elem_index<3>(tid, a, lo, logN);
-    default: return elem_index<4>(tid, a, lo, logN);
-  }
-}
-__device__ __forceinline__ int inv_first_index(int tid, int a, int logN) {
-  return elem_index<4>(tid, a, 0, logN);
-}
-__device__ __forceinline__ int inv_last_index(int tid, int a, int logN) {
-  int lo, b;
-  inv_geom(n_passes(logN) - 1, logN, lo, b);
-  switch (b) {
-    case 1: return elem_index<1>(tid, a, lo, logN);
-    case 2: return elem_index<2>(tid, a, lo, logN);
-    case 3: return elem_index<3>(tid, a, lo, logN);
-    default: return elem_index<4>(tid, a, lo, logN);
+template <int LOGN, int J>
+__device__ __forceinline__ void fwd_from(uint64_t (&v)[16], uint64_t* lds, int tid,
+                                         const u64x2* __restrict__ tw, uint64_t q) {
+  using S = NttShape<LOGN>;
+  constexpr int LO = S::fwd_lo(J), B = S::fwd_b(J);
+  fwd_pass<LOGN, B, LO, J == 0>(v, tid, tw, q);
+  if constexpr (J + 1 < S::P) {
+    // Within later passes a thread stores exactly the positions it loaded,
+    // so one barrier before the first store (guarding LDS still read by an
+    // earlier transform of the workgroup) and one per exchange suffice.
+    if (J == 0) __syncthreads();
+    lds_store<LOGN, B, LO>(v, lds, tid);
+    __syncthreads();
+    lds_load<LOGN, S::fwd_b(J + 1), S::fwd_lo(J + 1)>(v, lds, tid);
+    fwd_from<LOGN, J + 1>(v, lds, tid, tw, q);
   }
 }
 
-// Forward transform of the residues in v (loaded with fwd_first_index);
-// returns them in [0, 4q) at fwd_last_index positions.  lds must hold
-// lds_pad(N) + 1 words; the caller synchronises before reusing it.
-__device__ __forceinline__ void ntt_fwd(uint64_t (&v)[16], uint64_t* lds, int logN, int tid,
-                                        const uint64_t* __restrict__ tw,
-                                        const uint64_t* __restrict__ twp, uint64_t q) {
-  const int P = n_passes(logN);
-  for (int j = 0; j < P; ++j) {
-    int lo, b;
-    fwd_geom(j, logN, lo, b);
-    if (j > 0) {
-      __syncthreads();
-      switch (b) {
-        case 1: lds_load<1>(v, lds, lo, logN, tid); break;
-        case 2: lds_load<2>(v, lds, lo, logN, tid); break;
-        case 3: lds_load<3>(v, lds, lo, logN, tid); break;
-        default: lds_load<4>(v, lds, lo, logN, tid);
-      }
-    }
-    switch (b) {
-      case 1: fwd_pass<1>(v, lo, logN, tid, tw, twp, q); break;
-      case 2: fwd_pass<2>(v, lo, logN, tid, tw, twp, q); break;
-      case 3: fwd_pass<3>(v, lo, logN, tid, tw, twp, q); break;
-      default: fwd_pass<4>(v, lo, logN, tid, tw, twp, q);
-    }
-    if (j + 1 < P) {
-      // Only the last pass may be narrower than four bits.  Within a pass a
-      // thread stores exactly the positions it loaded, so the one barrier
-      // needed before the first store guards LDS still being read by a
-      // previous transform of the same workgroup.
-      if (j == 0) __syncthreads();
-      lds_store<4>(v, lds, lo, logN, tid);
-    }
+template <int LOGN, int J>
+__device__ __forceinline__ void inv_from(uint64_t (&v)[16], uint64_t* lds, int tid,
+                                         const u64x2* __restrict__ tw, const Prime& P) {
+  using S = NttShape<LOGN>;
+  constexpr int LO = S::inv_lo(J), B = S::inv_b(J);
+  inv_pass<LOGN, B, LO, J == 0, J + 1 == S::P>(v, tid, tw, P);
+  if constexpr (J + 1 < S::P) {
+    if (J == 0) __syncthreads();
+    lds_store<LOGN, B, LO>(v, lds, tid);
+    __syncthreads();
+    lds_load<LOGN, S::inv_b(J + 1), S::inv_lo(J + 1)>(v, lds, tid);
+    inv_from<LOGN, J + 1>(v, lds, tid, tw, P);
   }
 }
 
-// Inverse transform (input at inv_first_index in [0, 2q), output at
-// inv_last_index in [0, 2q), not yet multiplied by N^-1).
-__device__ __forceinline__ void ntt_inv(uint64_t (&v)[16], uint64_t* lds, int logN, int tid,
-                                        const uint64_t* __restrict__ tw,
-                                        const uint64_t* __restrict__ twp, uint64_t q) {
-  const int P = n_passes(logN);
-  for (int j = 0; j < P; ++j) {
-    int lo, b;
-    inv_geom(j, logN, lo, b);
-    if (j > 0) {
-      __syncthreads();
-      switch (b) {
-        case 1: lds_load<1>(v, lds, lo, logN, tid); break;
-        case 2: lds_load<2>(v, lds, lo, logN, tid); break;
-        case 3: lds_load<3>(v, lds, lo, logN, tid); break;
-        default: lds_load<4>(v, lds, lo, logN, tid);
-      }
-    }
-    switch (b) {
-      case 1: inv_pass<1>(v, lo, logN, tid, tw, twp, q); break;
-      case 2: inv_pass<2>(v, lo, logN, tid, tw, twp, q); break;
-      case 3: inv_pass<3>(v, lo, logN, tid, tw, twp, q); break;
-      default: inv_pass<4>(v, lo, logN, tid, tw, twp, q);
-    }
-    if (j + 1 < P) {
-      if (j == 0) __syncthreads();
-      lds_store<4>(v, lds, lo, logN, tid);
-    }
-  }
+// Forward transform.  Input: residues below q, slot a = coefficient
+// coef_index(tid, a).  Output: slot a = evaluation a + 16 tid in [0, q).
+// lds holds NttShape<LOGN>::lds_bytes; the caller synchronises before reusing it.
+template <int LOGN>
+__device__ __forceinline__ void ntt_fwd(uint64_t (&v)[16], uint64_t* lds, int tid,
+                                        const u64x2* __restrict__ tw, uint64_t q) {
+  fwd_from<LOGN, 0>(v, lds, tid, tw, q);
+#pragma unroll
+  for (int a = 0; a < 16; ++a) v[a] = csub(csub(csub(v[a], 4 * q), 2 * q), q);
+}
+
+// Inverse transform times N^-1.  Input: residues below q, slot a = evaluation
+// a + 16 tid (the forward's output order).  Output: slot a = coefficient
+// coef_index(tid, a) in [0, q).  tw points at the limb's inverse table.
+template <int LOGN>
+__device__ __forceinline__ void ntt_inv(uint64_t (&v)[16], uint64_t* lds, int tid,
+                                        const u64x2* __restrict__ tw, const Prime& P) {
+  inv_from<LOGN, 0>(v, lds, tid, tw, P);
+#pragma unroll
+  for (int a = 0; a < 16; ++a) v[a] = csub(csub(v[a], 2 * P.q), P.q);
 }
 
 }  // namespace sanns

@@ -110,14 +110,19 @@ std::vector<uint64_t> twiddle_table(uint32_t N, uint64_t q, uint64_t psi) {
     pw[i] = mulmod(pw[i - 1], psi, q);
     ipw[i] = mulmod(ipw[i - 1], ipsi, q);
   }
+  // [0, 2N): forward pairs; [2N, 4N): inverse pairs
   std::vector<uint64_t> t(4 * (size_t)N);
   for (uint32_t m = 0; m < N; ++m) {
     const uint32_t r = bitrev(m, logN);
-    t[m] = pw[r];
-    t[N + m] = shoup_companion(pw[r], q);
-    t[2 * (size_t)N + m] = ipw[r];
-    t[3 * (size_t)N + m] = shoup_companion(ipw[r], q);
+    t[2 * (size_t)m] = pw[r];
+    t[2 * (size_t)m + 1] = shoup_companion(pw[r], q);
+    t[2 * (size_t)N + 2 * m] = ipw[r];
+    t[2 * (size_t)N + 2 * m + 1] = shoup_companion(ipw[r], q);
   }
+  // inverse entry 0 (no stage uses it): the last stage's twiddle times N^-1
+  const uint64_t merged = mulmod(ipw[bitrev(1, logN)], powmod(N % q, q - 2, q), q);
+  t[2 * (size_t)N] = merged;
+  t[2 * (size_t)N + 1] = shoup_companion(merged, q);
   return t;
 }
 

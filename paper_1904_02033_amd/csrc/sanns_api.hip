@@ -305,7 +305,8 @@ extern "C" sanns_status sanns_ctx_create(const sanns_params* p, int device, sann
     sanns_ctx_destroy(ctx);
     return fail(SANNS_E_DEVICE, "context setup: %s", hipGetErrorString(e));
   }
-  for (uint32_t l = 0; l < L; ++l) ctx->tws.tw[l] = ctx->d_tw + (size_t)l * 4 * N;
+  for (uint32_t l = 0; l < L; ++l)
+    ctx->tws.tw[l] = reinterpret_cast<const u64x2*>(ctx->d_tw + (size_t)l * 4 * N);
   *out = ctx;
   return SANNS_OK;
 }
