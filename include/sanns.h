@@ -78,6 +78,8 @@ typedef struct {
 #define SANNS_MODE_PLAIN 0   /* one kernel launch per ciphertext operation    */
 #define SANNS_MODE_FUSED 1   /* fused NTT / multiply-accumulate / INTT+mask   */
 #define SANNS_MODE_BATCHED 2 /* fused kernels replayed from a cached hipGraph */
+#define SANNS_MODE_PERSISTENT 3 /* one persistent work-queue launch of all phases,
+                                   replayed from a cached hipGraph              */
 
 typedef struct sanns_ctx sanns_ctx;
 
@@ -218,16 +220,22 @@ size_t sanns_distances_workspace(const sanns_ctx *ctx, const sanns_db *db,
  *   query_ids     dev [Q] uint64
  *   work          host [M][2] uint32 or NULL (see above); entries outside
  *                 Q x n_chunks are rejected with SANNS_E_RANGE
- *   mode          SANNS_MODE_PLAIN, SANNS_MODE_FUSED or SANNS_MODE_BATCHED;
- *                 all three give bit-identical outputs
+ *   mode          SANNS_MODE_PLAIN, SANNS_MODE_FUSED, SANNS_MODE_BATCHED or
+ *                 SANNS_MODE_PERSISTENT (2048 <= N <= 16384, d <= 252); all
+ *                 give bit-identical outputs
  *   ct_out        dev [M][2][L][N] uint64, coefficient form
  *   server_share  dev [M][N] uint32
  *   workspace     dev, at least sanns_distances_workspace() bytes
  * SANNS_MODE_BATCHED captures the launches into a hipGraph cached in the
  * context under the call's pointers and sizes and replays it on later calls
  * with the same ones (new contents of every device buffer, query_ids
- * included, are picked up; the mask_key bytes are part of the cache key).  Errors: SANNS_E_INVALID,
- * SANNS_E_WORKSPACE, SANNS_E_DEVICE. */
+ * included, are picked up; the mask_key bytes are part of the cache key).
+ * SANNS_MODE_PERSISTENT runs the whole call as one launch of a work-queue
+ * kernel (after a reset of its control words in the workspace): query NTTs
+ * and mask rows first, then the multiply-accumulate tiles, then INTT + mask,
+ * each phase entered once the items it reads are published device-wide; it
+ * is captured and replayed the same way.  Calls that share a workspace must
+ * not overlap.  Errors: SANNS_E_INVALID, SANNS_E_WORKSPACE, SANNS_E_DEVICE. */
 sanns_status sanns_distances(sanns_ctx *ctx, const sanns_db *db,
                              const uint64_t *ct_in, uint32_t Q,
                              const uint8_t *mask_key,
@@ -239,13 +247,16 @@ sanns_status sanns_distances(sanns_ctx *ctx, const sanns_db *db,
 /* Synchronise `stream` and return (and clear) the context's device error
  * word: SANNS_E_RANGE if, since the last call, an input residue was >= q_l
  * or a slot index of sanns_encode_db was outside [-1, n) (such a slot is
- * encoded as padding). */
+ * encoded as padding); SANNS_E_DEVICE if a persistent launch gave up waiting
+ * for a phase (its bounded wait expired; outputs are undefined). */
 sanns_status sanns_device_status(sanns_ctx *ctx, void *stream);
 
 /* Fix the multiply-accumulate schedule (used by the autotuner):
  *   lds_variant  LDS-staged kernel used for batches of >= 2 queries against
  *                every chunk (work == NULL): 1..11 (register-staged) or 21..27
- *                (direct-to-LDS staged), or 0 for the default;
+ *                (direct-to-LDS staged), or 0 for the default; or the tile
+ *                shape of SANNS_MODE_PERSISTENT: 41..44 (N = 8192), 51..52
+ *                (N = 4096), 61 (N = 2048), 71 (N = 16384);
  *   qt x ct      register tile (queries x chunks per thread) used for every
  *                other call: 1x1, 1x2, 1x4, 1x8, 2x2, 2x4, 4x2, 2x3, 3x2, or
  *                0x0 for the automatic choice.
@@ -264,6 +275,7 @@ sanns_status sanns_set_schedule(sanns_ctx *ctx, int lds_variant, int qt, int ct)
  * sanns_distances in SANNS_MODE_FUSED or SANNS_MODE_BATCHED records a HIP
  * event pair around each phase's launch on the caller's stream (batched
  * calls then launch the kernels directly instead of replaying the graph).
+ * SANNS_MODE_PERSISTENT calls are not timed per phase.
  * Enabling resets the accumulated times. */
 sanns_status sanns_profile_enable(sanns_ctx *ctx, int on);
 

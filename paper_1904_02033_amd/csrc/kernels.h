@@ -34,6 +34,25 @@ struct MaskKey {
   uint32_t k[8];
 };
 
+// Arguments of the persistent whole-batch kernel.
+struct PersistArgs {
+  const uint64_t* ct_in;    // [Q][d][2][L][N] coefficient form
+  uint64_t* qntt;           // workspace: query NTT form, 27-bit halves
+  const uint2* db;          // [L][C][d][N] halves
+  const uint32_t* norms;    // [C][N]
+  const uint64_t* qids;     // [Q]
+  const uint32_t* work;     // [M][2] (query, chunk) or null for all pairs
+  const void* tiles;        // MacTile<TQT, TCT>[n_tiles] when work is set
+  uint64_t* ct_out;         // [M][2][L][N]
+  uint32_t* share;          // [M][N]
+  uint32_t* ctrl;           // kCtrlWords control words
+  uint32_t* err;            // sticky error word
+  int Q, d, L, C, M, n_tiles;
+  uint32_t t;
+  uint64_t tone;
+  MaskKey K;
+};
+
 // One tile of the multiply-accumulate schedule: QT queries x CT chunks; the
 // output index of pair (a, b) is out[a][b], -1 when the pair is padding.
 template <int QT, int CT>

@@ -34,17 +34,17 @@ __device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, const Prime& 
 // forward / inverse transforms of independent polynomials
 // --------------------------------------------------------------------------
 
-// One polynomial per workgroup; polynomial p uses limb p % L.  With split
-// set the output residues are stored as their 27-bit halves (uint2), the
-// form the multiply-accumulate kernels consume.
+// Forward transform of polynomial p (limb p % L) by one workgroup.  With
+// split set the output residues are stored as their 27-bit halves (uint2),
+// the form the multiply-accumulate kernels consume.
 template <int LOGN>
-__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
-k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int L, PrimeSet ps,
-          TwSet tws, uint32_t* err, int split) {
-  extern __shared__ uint64_t lds[];
+__device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
+                                             const uint64_t* __restrict__ in,
+                                             uint64_t* __restrict__ out, int L,
+                                             const PrimeSet& ps, const TwSet& tws,
+                                             uint32_t* err, int split) {
   constexpr int N = NttShape<LOGN>::N;
-  const int tid = threadIdx.x;
-  const int p = blockIdx.x, l = p % L;
+  const int l = p % L;
   const Prime& P = ps.p[l];
   const uint64_t* src = in + (size_t)p * N;
   uint64_t v[16];
@@ -69,6 +69,15 @@ k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int L, Pr
 #pragma unroll
     for (int a = 0; a < 16; ++a) dst[ntt_slot<LOGN>(tid, a)] = v[a];
   }
+}
+
+// One polynomial per workgroup.
+template <int LOGN>
+__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
+k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int L, PrimeSet ps,
+          TwSet tws, uint32_t* err, int split) {
+  extern __shared__ uint64_t lds[];
+  ntt_fwd_poly<LOGN>(blockIdx.x, threadIdx.x, lds, in, out, L, ps, tws, err, split);
 }
 
 // In-place inverse transform, result multiplied by N^-1 and in [0, q).
@@ -145,7 +154,20 @@ __device__ __forceinline__ void work_pair(const uint32_t* work, int m, int C, in
   }
 }
 
-// Thread per (output m, block b): masks of slots 4b .. 4b+3.
+// Masks of slots 4b .. 4b+3 of output row m (query id, chunk k).
+__device__ __forceinline__ void mask_block(const MaskKey& K, uint64_t id, int k, int b,
+                                           uint32_t t, uint64_t tone, uint32_t* __restrict__ row) {
+  uint32_t o[16];
+  chacha_block(K, (uint32_t)b, (uint32_t)id, (uint32_t)(id >> 32), (uint32_t)k, o);
+  uint4 r;
+  r.x = mod_t_128(o[0], o[1], o[2], o[3], t, tone);
+  r.y = mod_t_128(o[4], o[5], o[6], o[7], t, tone);
+  r.z = mod_t_128(o[8], o[9], o[10], o[11], t, tone);
+  r.w = mod_t_128(o[12], o[13], o[14], o[15], t, tone);
+  reinterpret_cast<uint4*>(row)[b] = r;
+}
+
+// Thread per (output m, block b).
 __global__ void __launch_bounds__(256)
 k_masks(MaskKey K, const uint64_t* __restrict__ qids, const uint32_t* __restrict__ work,
         int C, int M, int N, uint32_t t, uint64_t tone, uint32_t* __restrict__ share) {
@@ -155,15 +177,7 @@ k_masks(MaskKey K, const uint64_t* __restrict__ qids, const uint32_t* __restrict
   const int m = (int)(g / nb), b = (int)(g % nb);
   int qi, k;
   work_pair(work, m, C, qi, k);
-  const uint64_t id = qids[qi];
-  uint32_t o[16];
-  chacha_block(K, (uint32_t)b, (uint32_t)id, (uint32_t)(id >> 32), (uint32_t)k, o);
-  uint4 r;
-  r.x = mod_t_128(o[0], o[1], o[2], o[3], t, tone);
-  r.y = mod_t_128(o[4], o[5], o[6], o[7], t, tone);
-  r.z = mod_t_128(o[8], o[9], o[10], o[11], t, tone);
-  r.w = mod_t_128(o[12], o[13], o[14], o[15], t, tone);
-  reinterpret_cast<uint4*>(share + (size_t)m * N)[b] = r;
+  mask_block(K, qids[qi], k, b, t, tone, share + (size_t)m * N);
 }
 
 // --------------------------------------------------------------------------
@@ -173,14 +187,14 @@ k_masks(MaskKey K, const uint64_t* __restrict__ qids, const uint32_t* __restrict
 // Polynomial p = (m 2 + c) L + l of ct_out: INTT, times N^-1, and for c = 0
 // add Delta_l [norm - r]_t at every coefficient.
 template <int LOGN>
-__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
-k_intt_mask(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
-            const uint32_t* __restrict__ norms, const uint32_t* __restrict__ work, int C,
-            int L, uint32_t t, PrimeSet ps, TwSet tws) {
-  extern __shared__ uint64_t lds[];
+__device__ __forceinline__ void intt_mask_poly(int p, int tid, uint64_t* lds,
+                                               uint64_t* __restrict__ ct,
+                                               const uint32_t* __restrict__ share,
+                                               const uint32_t* __restrict__ norms,
+                                               const uint32_t* __restrict__ work, int C, int L,
+                                               uint32_t t, const PrimeSet& ps, const TwSet& tws) {
   constexpr int N = NttShape<LOGN>::N;
-  const int tid = threadIdx.x;
-  const int p = blockIdx.x, l = p % L, c = (p / L) & 1, m = p / (2 * L);
+  const int l = p % L, c = (p / L) & 1, m = p / (2 * L);
   const Prime& P = ps.p[l];
   uint64_t* buf = ct + (size_t)p * N;
   uint64_t v[16];
@@ -200,9 +214,18 @@ k_intt_mask(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
       v[a] = addmod(v[a], shoup(mv, P.delta, P.deltap, P.q), P.q);
     }
   }
-  __syncthreads();
+  __syncthreads();  // every thread has read its inputs before any overwrite
 #pragma unroll
   for (int a = 0; a < 16; ++a) buf[coef_index<LOGN>(tid, a)] = v[a];
+}
+
+template <int LOGN>
+__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
+k_intt_mask(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
+            const uint32_t* __restrict__ norms, const uint32_t* __restrict__ work, int C,
+            int L, uint32_t t, PrimeSet ps, TwSet tws) {
+  extern __shared__ uint64_t lds[];
+  intt_mask_poly<LOGN>(blockIdx.x, threadIdx.x, lds, ct, share, norms, work, C, L, t, ps, tws);
 }
 
 // --------------------------------------------------------------------------
@@ -231,15 +254,13 @@ __device__ __forceinline__ MacTile<QT, CT> regular_tile(int y, int Q, int C) {
   return T;
 }
 
-template <int QT, int CT>
-__global__ void __launch_bounds__(256)
-k_mac(const uint2* __restrict__ qntt, const uint2* __restrict__ db,
-      const MacTile<QT, CT>* __restrict__ tiles, int Q, int d, int L, int logN, int C,
-      PrimeSet ps, uint64_t* __restrict__ out) {
-  const int N = 1 << logN;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  const int l = blockIdx.z;
-  const MacTile<QT, CT> T = tiles ? tiles[blockIdx.y] : regular_tile<QT, CT>(blockIdx.y, Q, C);
+// WIDE = false: d <= 255, a single accumulation without folded partials.
+template <int QT, int CT, bool WIDE = true>
+__device__ __forceinline__ void mac_reg_slot(const MacTile<QT, CT>& T, int s, int l,
+                                             const uint2* __restrict__ qntt,
+                                             const uint2* __restrict__ db, int d, int L, int N,
+                                             int C, const PrimeSet& ps,
+                                             uint64_t* __restrict__ out) {
   const Prime& P = ps.p[l];
   const size_t qstride_i = (size_t)2 * L * N;                 // next coordinate
   const size_t dbstride_i = (size_t)N;
@@ -258,8 +279,10 @@ k_mac(const uint2* __restrict__ qntt, const uint2* __restrict__ db,
 #pragma unroll
       for (int b = 0; b < CT; ++b) res[a][c][b] = 0;
 
-  for (int i0 = 0; i0 < d; i0 += 255) {
-    const int i1 = d - i0 < 255 ? d : i0 + 255;
+  // WIDE: folds of 255 coordinates added into res; otherwise one pass.
+  const int step = WIDE ? 255 : d;
+  for (int i0 = 0; i0 < d; i0 += step) {
+    const int i1 = d - i0 < step ? d : i0 + step;
     Acc3 acc[QT][2][CT];
 #pragma unroll
     for (int a = 0; a < QT; ++a)
@@ -326,7 +349,9 @@ k_mac(const uint2* __restrict__ qntt, const uint2* __restrict__ db,
       for (int c = 0; c < 2; ++c)
 #pragma unroll
         for (int b = 0; b < CT; ++b)
-          res[a][c][b] = addmod(res[a][c][b], acc3_reduce(acc[a][c][b], P), P.q);
+          res[a][c][b] = WIDE ? addmod(res[a][c][b], acc3_reduce(acc[a][c][b], P), P.q)
+                              : acc3_reduce(acc[a][c][b], P);
+    if (!WIDE) break;
   }
 #pragma unroll
   for (int a = 0; a < QT; ++a)
@@ -337,6 +362,16 @@ k_mac(const uint2* __restrict__ qntt, const uint2* __restrict__ db,
 #pragma unroll
       for (int c = 0; c < 2; ++c) out[(((size_t)o * 2 + c) * L + l) * N + s] = res[a][c][b];
     }
+}
+
+template <int QT, int CT>
+__global__ void __launch_bounds__(256)
+k_mac(const uint2* __restrict__ qntt, const uint2* __restrict__ db,
+      const MacTile<QT, CT>* __restrict__ tiles, int Q, int d, int L, int logN, int C,
+      PrimeSet ps, uint64_t* __restrict__ out) {
+  const MacTile<QT, CT> T = tiles ? tiles[blockIdx.y] : regular_tile<QT, CT>(blockIdx.y, Q, C);
+  mac_reg_slot<QT, CT>(T, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.z, qntt, db, d, L,
+                       1 << logN, C, ps, out);
 }
 
 // LDS-staged multiply-accumulate for the every-query-against-every-chunk
@@ -548,29 +583,35 @@ k_mac_lds(const uint2* __restrict__ qntt, const uint2* __restrict__ db, int Q, i
 // registers are spent on staging and the query words arrive already split.
 // LDS buffer B0/B1 alternate: the next step is loaded into one while the
 // other is multiplied.
+// LDS footprint of one direct-to-LDS tile: two query and two database buffers.
+template <int QT, int CT, int QG, int CG, int S, int DI>
+struct MacDlShape {
+  static constexpr int QU = QT * QG * 2 * DI * (S / 2), DU = CT * CG * DI * (S / 2);
+  static constexpr size_t lds_bytes = (size_t)2 * (QU + DU) * sizeof(uint4);
+};
+
+// Tile lin of the all-pairs schedule (query tile fastest, then chunk tile,
+// then limb, then slot range), computed by the NT = S QG CG threads of a
+// workgroup with the given LDS buffers.
 template <int QT, int CT, int QG, int CG, int S, int DI, int UNR, bool WIDE>
-__global__ void __launch_bounds__(S * QG * CG)
-k_mac_dl(const uint2* __restrict__ qntt, const uint2* __restrict__ db, int Q, int d, int L,
-         int logN, int C, int n_blocks, PrimeSet ps, uint64_t* __restrict__ out) {
+__device__ __forceinline__ void mac_dl_tile(int lin, int tid, uint4* sq0, uint4* sq1, uint4* sd0,
+                                            uint4* sd1, const uint2* __restrict__ qntt,
+                                            const uint2* __restrict__ db, int Q, int d, int L,
+                                            int logN, int C, const PrimeSet& ps,
+                                            uint64_t* __restrict__ out) {
   constexpr int QB = QT * QG, CB = CT * CG, NT = S * QG * CG;
   constexpr int FOLD = (255 / DI) * DI;
   constexpr int H = S / 2;                            // 16-byte units per row of S slots
   constexpr int QU = QB * 2 * DI * H, DU = CB * DI * H;  // 16-byte units per step
   constexpr int NQU = (QU + NT - 1) / NT, NDU = (DU + NT - 1) / NT;
-  __shared__ uint4 sq0[QU], sq1[QU];
-  __shared__ uint4 sd0[DU], sd1[DU];
   const int N = 1 << logN;
   const int nqt = (Q + QB - 1) / QB, nct = (C + CB - 1) / CB;
-  const int per_xcd = (n_blocks + 7) >> 3;
-  const int lin = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (lin >= n_blocks) return;
   const int y = lin % (nqt * nct);
   const int sl = lin / (nqt * nct);
   const int l = sl % L, st = sl / L;
   const int q0 = (y % nqt) * QB, k0 = (y / nqt) * CB;
   const int s0 = st * S;
   const Prime& P = ps.p[l];
-  const int tid = threadIdx.x;
   const int s = tid % S, g = tid / S, gq = g % QG, gc = g / QG;
   const int wbase = __builtin_amdgcn_readfirstlane(tid) & ~63;
 
@@ -693,6 +734,187 @@ k_mac_dl(const uint2* __restrict__ qntt, const uint2* __restrict__ db, int Q, in
     __syncthreads();
   }
   mac_store<QT, CT>(acc, res, WIDE, P, q0, k0, gq, gc, Q, C, L, l, N, s0 + s, out);
+}
+
+template <int QT, int CT, int QG, int CG, int S, int DI, int UNR, bool WIDE>
+__global__ void __launch_bounds__(S * QG * CG)
+k_mac_dl(const uint2* __restrict__ qntt, const uint2* __restrict__ db, int Q, int d, int L,
+         int logN, int C, int n_blocks, PrimeSet ps, uint64_t* __restrict__ out) {
+  using SH = MacDlShape<QT, CT, QG, CG, S, DI>;
+  __shared__ uint4 sq0[SH::QU], sq1[SH::QU];
+  __shared__ uint4 sd0[SH::DU], sd1[SH::DU];
+  const int per_xcd = (n_blocks + 7) >> 3;
+  const int lin = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (lin >= n_blocks) return;
+  mac_dl_tile<QT, CT, QG, CG, S, DI, UNR, WIDE>(lin, threadIdx.x, sq0, sq1, sd0, sd1, qntt, db,
+                                                Q, d, L, logN, C, ps, out);
+}
+
+// --------------------------------------------------------------------------
+// the whole batch as one persistent launch
+// --------------------------------------------------------------------------
+
+// Control words of the persistent schedule (zeroed before each launch).
+enum : int {
+  kTicket1 = 0,   // query NTT and mask-row items
+  kTicketMac = 1, // eight multiply-accumulate queues, one per XCD
+  kTicket3 = 9,   // INTT + mask items
+  kDoneNtt = 10,
+  kDoneMasks = 11,
+  kDoneMac = 12,
+  kAbort = 13,
+  kCtrlWords = kPersistCtrlWords
+};
+constexpr uint32_t kSpinLimit = 1u << 25;  // about 7 s of 200 ns sleeps
+
+__global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+
+// Physical XCD of the calling wave (hardware register XCC_ID, bits 0..3).
+__device__ __forceinline__ int xcd_id() {
+  return (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & 7u);
+}
+
+// Thread 0 waits until ctrl[idx] >= target (acquire); false on abort or
+// time-out, which also raises the abort word so that every waiter leaves.
+__device__ bool wait_at_least(uint32_t* ctrl, int idx, uint32_t target, uint32_t* err) {
+  for (uint32_t spins = 0;; ++spins) {
+    if (__hip_atomic_load(ctrl + idx, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) >= target)
+      return true;
+    if (__hip_atomic_load(ctrl + kAbort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    if (spins >= kSpinLimit) {
+      atomicOr(err, 4u);
+      __hip_atomic_store(ctrl + kAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(8);
+  }
+}
+
+// Needs d <= (255 / DI) DI (one accumulation pass per tile).
+// Work items, in ticket order (an item only depends on items of earlier
+// phases, so the schedule needs no co-residency and cannot deadlock):
+//   phase 1: forward NTT of each query polynomial, then each output row's
+//            masks (no dependencies);
+//   phase 2: multiply-accumulate tiles, split into eight contiguous ranges
+//            served first to the blocks of the matching XCD (so that the
+//            query tiles sharing a database tile share that XCD's L2), then
+//            stolen by any block;
+//   phase 3: INTT + mask of each output polynomial.
+// A block publishes how many items of a phase it finished (one device-wide
+// release) when it leaves the phase, and waits (one acquire) for the counts
+// a phase depends on when it enters it.
+template <int LOGN, int QT, int CT, int QG, int CG, int DI, int TQT, int TCT>
+__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
+k_persistent(PersistArgs A, PrimeSet ps, TwSet tws) {
+  constexpr int T = NttShape<LOGN>::T, N = NttShape<LOGN>::N;
+  constexpr int S = T / (QG * CG);
+  using SH = MacDlShape<QT, CT, QG, CG, S, DI>;
+  static_assert(S * QG * CG == T && S >= 2, "tile does not match the workgroup");
+  extern __shared__ uint64_t lds[];
+  __shared__ int s_ticket, s_ok;
+  const int tid = threadIdx.x;
+  uint32_t* ctrl = A.ctrl;
+  const int L = A.L;
+  const int n_ntt = A.Q * A.d * 2 * L;
+  const int n1 = n_ntt + A.M;
+
+  // ---- phase 1
+  uint32_t done_ntt = 0, done_masks = 0;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_ticket = (int)atomicAdd(ctrl + kTicket1, 1u);
+    __syncthreads();
+    const int tk = s_ticket;
+    if (tk >= n1) break;
+    if (tk < n_ntt) {
+      ntt_fwd_poly<LOGN>(tk, tid, lds, A.ct_in, A.qntt, L, ps, tws, A.err, 1);
+      ++done_ntt;
+    } else {
+      const int m = tk - n_ntt;
+      int qi, k;
+      work_pair(A.work, m, A.C, qi, k);
+      const uint64_t id = A.qids[qi];
+      for (int b = tid; b < (N >> 2); b += T)
+        mask_block(A.K, id, k, b, A.t, A.tone, A.share + (size_t)m * N);
+      ++done_masks;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    if (done_ntt) atomicAdd(ctrl + kDoneNtt, done_ntt);
+    if (done_masks) atomicAdd(ctrl + kDoneMasks, done_masks);
+    s_ok = wait_at_least(ctrl, kDoneNtt, (uint32_t)n_ntt, A.err);
+  }
+  __syncthreads();
+  if (!s_ok) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+
+  // ---- phase 2
+  const uint2* qn = reinterpret_cast<const uint2*>(A.qntt);
+  uint4* sq0 = reinterpret_cast<uint4*>(lds);
+  uint4* sq1 = sq0 + SH::QU;
+  uint4* sd0 = sq1 + SH::QU;
+  uint4* sd1 = sd0 + SH::DU;
+  int n_mac;
+  if (A.work) {
+    n_mac = A.n_tiles * (N / T) * L;
+  } else {
+    const int nqt = (A.Q + QT * QG - 1) / (QT * QG), nct = (A.C + CT * CG - 1) / (CT * CG);
+    n_mac = nqt * nct * L * (N / S);
+  }
+  const int per_q = (n_mac + 7) >> 3;
+  const int home = xcd_id();
+  uint32_t done_mac = 0;
+  for (int j = 0; j < 8; ++j) {
+    const int x = (home + j) & 7;
+    const int lo = x * per_q, hi = min(n_mac, lo + per_q);
+    for (;;) {
+      __syncthreads();
+      if (tid == 0) s_ticket = lo + (int)atomicAdd(ctrl + kTicketMac + x, 1u);
+      __syncthreads();
+      const int lin = s_ticket;
+      if (lin >= hi) break;
+      if (A.work) {
+        // (tile, slot range, limb), slot range fastest
+        const int r = lin % (N / T), jl = lin / (N / T);
+        const int tile = jl % A.n_tiles, l = jl / A.n_tiles;
+        const MacTile<TQT, TCT> Tl =
+            reinterpret_cast<const MacTile<TQT, TCT>*>(A.tiles)[tile];
+        mac_reg_slot<TQT, TCT, false>(Tl, r * T + tid, l, qn, A.db, A.d, L, N, A.C, ps,
+                                      A.ct_out);
+      } else {
+        mac_dl_tile<QT, CT, QG, CG, S, DI, 1, false>(lin, tid, sq0, sq1, sd0, sd1, qn, A.db,
+                                                     A.Q, A.d, L, LOGN, A.C, ps, A.ct_out);
+      }
+      ++done_mac;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    if (done_mac) atomicAdd(ctrl + kDoneMac, done_mac);
+    s_ok = wait_at_least(ctrl, kDoneMac, (uint32_t)n_mac, A.err) &&
+           wait_at_least(ctrl, kDoneMasks, (uint32_t)A.M, A.err);
+  }
+  __syncthreads();
+  if (!s_ok) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+
+  // ---- phase 3
+  const int n3 = A.M * 2 * L;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_ticket = (int)atomicAdd(ctrl + kTicket3, 1u);
+    __syncthreads();
+    const int tk = s_ticket;
+    if (tk >= n3) break;
+    intt_mask_poly<LOGN>(tk, tid, lds, A.ct_out, A.share, A.norms, A.work, A.C, L, A.t, ps, tws);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -1164,6 +1386,74 @@ int mac_lds_min_n(int variant) {
 #undef SANNS_LDS_S
     default:
       return 0;
+  }
+}
+
+int persistent_logn(int shape) {
+  switch (shape) {
+#define SANNS_PS_LOGN(id, lg, qt, ct, qg, cg, di) \
+  case id:                                       \
+    return lg;
+    SANNS_PERSIST_SHAPES(SANNS_PS_LOGN)
+#undef SANNS_PS_LOGN
+    default:
+      return 0;
+  }
+}
+
+int persistent_max_d(int shape) {
+  switch (shape) {
+#define SANNS_PS_MAXD(id, lg, qt, ct, qg, cg, di) \
+  case id:                                       \
+    return (255 / di) * di;
+    SANNS_PERSIST_SHAPES(SANNS_PS_MAXD)
+#undef SANNS_PS_MAXD
+    default:
+      return 0;
+  }
+}
+
+int persistent_default_shape(int logN) {
+  switch (logN) {
+    case 11: return 61;
+    case 12: return 51;
+    case 13: return 41;
+    case 14: return 71;
+    default: return 0;
+  }
+}
+
+template <int LOGN, int QT, int CT, int QG, int CG, int DI>
+static hipError_t launch_persistent_t(const PersistArgs& A, const PrimeSet& ps,
+                                      const TwSet& tws, hipStream_t st) {
+  constexpr int T = NttShape<LOGN>::T, S = T / (QG * CG);
+  constexpr size_t lds_mac = MacDlShape<QT, CT, QG, CG, S, DI>::lds_bytes;
+  constexpr size_t lds = lds_mac > NttShape<LOGN>::lds_bytes ? lds_mac : NttShape<LOGN>::lds_bytes;
+  auto kern = k_persistent<LOGN, QT, CT, QG, CG, DI, kPersistTileQ, kPersistTileC>;
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, T, lds);
+  if (e != hipSuccess) return e;
+  long items = (long)A.Q * A.d * 2 * A.L + A.M;
+  long blocks = (long)cus * (per_cu > 0 ? per_cu : 1);
+  if (blocks > items) blocks = items;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, A.ctrl, kPersistCtrlWords, 0u);
+  hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(T), lds, st, A, ps, tws);
+  return hipGetLastError();
+}
+
+hipError_t launch_persistent(int shape, const PersistArgs& A, const PrimeSet& ps,
+                             const TwSet& tws, hipStream_t st) {
+  switch (shape) {
+#define SANNS_PS_CASE(id, lg, qt, ct, qg, cg, di) \
+  case id:                                       \
+    return launch_persistent_t<lg, qt, ct, qg, cg, di>(A, ps, tws, st);
+    SANNS_PERSIST_SHAPES(SANNS_PS_CASE)
+#undef SANNS_PS_CASE
+    default:
+      return hipErrorInvalidValue;
   }
 }
 

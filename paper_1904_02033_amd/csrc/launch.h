@@ -56,6 +56,27 @@ size_t mac_tile_bytes(int QT, int CT);  // 0 for a shape that is not built
 hipError_t launch_mac_lds(int variant, const uint2* qntt, const uint2* db, int Q, int d, int L,
                           int logN, int C, const PrimeSet& ps, uint64_t* out, hipStream_t st);
 int mac_lds_min_n(int variant);  // slots per block (N must be a multiple); 0 if unknown
+// Shapes of the persistent whole-batch kernel:
+// X(id, LOGN, QT, CT, QG, CG, DI): one workgroup of N/16 threads per item; the
+// multiply-accumulate tiles are direct-to-LDS tiles of QG QT queries x CG CT
+// chunks over S = N / (16 QG CG) slots.  Work lists use 2 x 2 register tiles.
+#define SANNS_PERSIST_SHAPES(X)          \
+  X(41, 13, 2, 2, 4, 4, 4)               \
+  X(42, 13, 1, 4, 4, 4, 4)               \
+  X(43, 13, 2, 2, 2, 8, 4)               \
+  X(44, 13, 1, 4, 8, 2, 4)               \
+  X(51, 12, 2, 2, 2, 4, 4)               \
+  X(52, 12, 1, 4, 2, 4, 4)               \
+  X(61, 11, 2, 2, 1, 4, 4)               \
+  X(71, 14, 2, 2, 4, 4, 2)
+constexpr int kPersistTileQ = 2, kPersistTileC = 2;
+constexpr int kPersistCtrlWords = 16;
+int persistent_logn(int shape);           // 0 if the shape is not built
+int persistent_default_shape(int logN);   // 0 if N is not supported
+int persistent_max_d(int shape);          // largest d the shape accumulates in one pass
+hipError_t launch_persistent(int shape, const PersistArgs& A, const PrimeSet& ps,
+                             const TwSet& tws, hipStream_t st);
+
 hipError_t launch_gather(const void* pts, int is_signed, long n, int d,
                          const int64_t* slot_point, long base, long total, int logN,
                          int16_t* gt, uint32_t* norms, uint32_t* err, hipStream_t st);

@@ -50,7 +50,7 @@ struct GraphKey {
   const void* ct_out;
   const void* share;
   const void* ws;
-  int qt, ct, lds, n_tiles, table;
+  int qt, ct, lds, n_tiles, table, persist;
   uint32_t key[8];
   bool operator<(const GraphKey& o) const { return std::memcmp(this, &o, sizeof *this) < 0; }
 };
@@ -75,7 +75,7 @@ struct sanns_ctx {
   size_t staging_bytes = 0;
   hipEvent_t staging_done = nullptr;
   // schedule override (0 = automatic)
-  int force_qt = 0, force_ct = 0, force_lds = 0;
+  int force_qt = 0, force_ct = 0, force_lds = 0, force_persist = 0;
   // per-phase profiling: one event pair per phase and call
   bool profiling = false;
   std::vector<std::vector<std::pair<hipEvent_t, hipEvent_t>>> prof_events;
@@ -213,7 +213,7 @@ sanns_status stage_upload(sanns_ctx* ctx, void* dst, const void* src, size_t byt
 }
 
 struct WsLayout {
-  size_t qntt, tiles, work, tmp, total;
+  size_t qntt, tiles, work, tmp, ctrl, total;
 };
 
 WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M) {
@@ -228,6 +228,8 @@ WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M) {
   off += align256((size_t)M * 2 * sizeof(uint32_t));
   w.tmp = off;
   off += align256(2 * L * N * 8);
+  w.ctrl = off;  // control words of the persistent schedule
+  off += align256(kPersistCtrlWords * sizeof(uint32_t));
   w.total = off;
   return w;
 }
@@ -340,6 +342,7 @@ extern "C" sanns_status sanns_device_status(sanns_ctx* ctx, void* stream) {
   HIP_TRY(hipMemset(ctx->d_err, 0, sizeof v));
   if (v & 1u) return fail(SANNS_E_RANGE, "an input residue was >= its prime");
   if (v & 2u) return fail(SANNS_E_RANGE, "a slot index was outside [-1, n)");
+  if (v & 4u) return fail(SANNS_E_DEVICE, "the persistent schedule timed out waiting for a phase");
   return SANNS_OK;
 }
 
@@ -382,12 +385,21 @@ extern "C" sanns_status sanns_profile_read(sanns_ctx* ctx, double* ms_out, int* 
 
 extern "C" sanns_status sanns_set_schedule(sanns_ctx* ctx, int lds_variant, int qt, int ct) {
   if (!ctx) return fail(SANNS_E_INVALID, "null context");
-  if (lds_variant < 0 || (lds_variant > 0 && mac_lds_min_n(lds_variant) == 0))
+  const bool persist = persistent_logn(lds_variant) != 0;
+  if (persist && persistent_logn(lds_variant) != ctx->logN)
+    return fail(SANNS_E_INVALID, "persistent shape %d is built for N = %d", lds_variant,
+                1 << persistent_logn(lds_variant));
+  if (lds_variant < 0 || (lds_variant > 0 && !persist && mac_lds_min_n(lds_variant) == 0))
     return fail(SANNS_E_INVALID, "LDS variant %d is not built", lds_variant);
   if (!(qt == 0 && ct == 0) && mac_tile_bytes(qt, ct) == 0)
     return fail(SANNS_E_INVALID, "tile %dx%d is not built", qt, ct);
   std::lock_guard<std::mutex> lock(ctx->mu);
-  ctx->force_lds = lds_variant;
+  if (persist) {
+    ctx->force_persist = lds_variant;
+  } else {
+    ctx->force_lds = lds_variant;
+    ctx->force_persist = 0;
+  }
   ctx->force_qt = qt;
   ctx->force_ct = ct;
   return SANNS_OK;
@@ -587,8 +599,17 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
   if (!ctx || !db || !db->mem || !ct_in || !mask_key || !query_ids || !ct_out ||
       !server_share || !workspace)
     return fail(SANNS_E_INVALID, "null argument");
-  if (mode != SANNS_MODE_PLAIN && mode != SANNS_MODE_FUSED && mode != SANNS_MODE_BATCHED)
+  if (mode != SANNS_MODE_PLAIN && mode != SANNS_MODE_FUSED && mode != SANNS_MODE_BATCHED &&
+      mode != SANNS_MODE_PERSISTENT)
     return fail(SANNS_E_INVALID, "bad mode %d", mode);
+  const int pshape = mode == SANNS_MODE_PERSISTENT
+                         ? (ctx->force_persist ? ctx->force_persist
+                                               : persistent_default_shape(ctx->logN))
+                         : 0;
+  if (mode == SANNS_MODE_PERSISTENT && pshape == 0)
+    return fail(SANNS_E_INVALID, "SANNS_MODE_PERSISTENT needs 2048 <= N <= 16384");
+  if (mode == SANNS_MODE_PERSISTENT && db && db->d > (uint32_t)persistent_max_d(pshape))
+    return fail(SANNS_E_INVALID, "SANNS_MODE_PERSISTENT needs d <= %d", persistent_max_d(pshape));
   if (Q == 0 || db->d == 0 || db->d > SANNS_MAX_D || db->n_chunks == 0)
     return fail(SANNS_E_INVALID, "bad shape");
   const uint32_t C = db->n_chunks;
@@ -633,6 +654,11 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
 
   int qt, ct, lds;
   choose_shape(ctx, Q, work == nullptr, qt, ct, lds);
+  if (pshape) {
+    qt = kPersistTileQ;
+    ct = kPersistTileC;
+    lds = 0;
+  }
   const void* dtiles = nullptr;
   const uint32_t* dwork = nullptr;
   int n_tiles;
@@ -650,11 +676,41 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
     n_tiles = (int)(((Q + qt - 1) / qt) * ((C + ct - 1) / ct));
   }
 
-  if (mode == SANNS_MODE_FUSED || ctx->profiling)
+  uint32_t* ctrl = (uint32_t*)(ws + W.ctrl);
+  auto enqueue = [&](hipStream_t s, bool profile) -> sanns_status {
+    if (!pshape)
+      return enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, lds, dtiles,
+                           n_tiles, ct_out, server_share, qntt, s, profile);
+    PersistArgs A;
+    A.ct_in = ct_in;
+    A.qntt = qntt;
+    A.db = (const uint2*)db->mem;
+    A.norms = (const uint32_t*)((const char*)db->mem + (size_t)ctx->p.L * C * db->d * ctx->p.N * 8);
+    A.qids = query_ids;
+    A.work = dwork;
+    A.tiles = dtiles;
+    A.ct_out = ct_out;
+    A.share = server_share;
+    A.ctrl = ctrl;
+    A.err = ctx->d_err;
+    A.Q = (int)Q;
+    A.d = (int)db->d;
+    A.L = (int)ctx->p.L;
+    A.C = (int)C;
+    A.M = (int)M;
+    A.n_tiles = n_tiles;
+    A.t = (uint32_t)ctx->p.t;
+    A.tone = ctx->tone;
+    A.K = K;
+    HIP_TRY(launch_persistent(pshape, A, ctx->ps, ctx->tws, s));
+    return SANNS_OK;
+  };
+
+  if (mode == SANNS_MODE_FUSED || (ctx->profiling && !pshape))
     return enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, lds, dtiles,
                          n_tiles, ct_out, server_share, qntt, st, ctx->profiling);
 
-  // batched: replay (or capture once) the fused sequence as a hipGraph
+  // batched and persistent: replay (or capture once) the sequence as a hipGraph
   GraphKey key;
   std::memset(&key, 0, sizeof key);
   key.db = db->mem;
@@ -672,14 +728,13 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
   key.lds = lds;
   key.n_tiles = n_tiles;
   key.table = work ? 1 : 0;
+  key.persist = pshape;
   std::memcpy(key.key, K.k, sizeof K.k);
   auto it = ctx->graphs.find(key);
   if (it == ctx->graphs.end()) {
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-    sanns_status s = enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, lds,
-                                   dtiles, n_tiles, ct_out, server_share, qntt,
-                                   ctx->cap_stream);
+    sanns_status s = enqueue(ctx->cap_stream, false);
     hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
     if (s != SANNS_OK) {
       if (graph) (void)hipGraphDestroy(graph);

@@ -29,7 +29,7 @@ SANNS_MAX_LIMBS = 4
 SANNS_MAX_D = 4096
 SANNS_FLAG_INSECURE_TEST = 1
 SANNS_U8, SANNS_I8 = 0, 1
-SANNS_MODE_PLAIN, SANNS_MODE_FUSED, SANNS_MODE_BATCHED = 0, 1, 2
+SANNS_MODE_PLAIN, SANNS_MODE_FUSED, SANNS_MODE_BATCHED, SANNS_MODE_PERSISTENT = 0, 1, 2, 3
 
 # Every exported symbol of include/sanns.h.
 EXPORTS = [
