@@ -91,6 +91,9 @@ def main():
                     choices=["batched-1Mx128", "batched-1Mx96", "linear-10Kx128",
                              "clustered-10M", "serving"])
     ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner and run the library's default batched schedule "
+                         "(used for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -143,7 +146,12 @@ def run_linear(args, w):
     # ------------------------------------------------ schedule (autotuned)
     from paper_1904_02033_amd import autotune
     tt = time.time()
-    best, timed = autotune.tune(ctx, db, ct, key, qids, reps=3)
+    if args.no_tune:
+        best = autotune.Schedule(nat.SANNS_MODE_BATCHED)
+        best.ms = float("nan")
+        timed = [best]
+    else:
+        best, timed = autotune.tune(ctx, db, ct, key, qids, reps=3)
     log(f"autotune {time.time() - tt:.1f}s: best {best.label()} {best.ms:.3f} ms; " +
         ", ".join(f"{c.label()} {c.ms:.2f}" for c in sorted(timed, key=lambda c: c.ms)[:6]))
 
@@ -197,7 +205,10 @@ def run_linear(args, w):
     mulacc = Q * C * 2 * d * L * N
     mac_ms = phases["mac"]
     mac_ops = 3 * mulacc  # 32x32->64 multiply-adds: Karatsuba on 27-bit halves
-    mac_kernel = "k_mac_dl" if pbest.variant >= 21 else ("k_mac_lds" if pbest.variant else "k_mac")
+    variant = pbest.variant or 22  # the library's default all-pairs schedule
+    mac_kernel = "k_mac_dl" if variant >= 21 else "k_mac_lds"
+    if Q < 2:
+        mac_kernel = "k_mac"
     if best.mode == nat.SANNS_MODE_PERSISTENT:
         mac_ms, mac_kernel = pct(step_ms, 50), "k_persistent (whole step)"
     mac_tops = mac_ops / (mac_ms * 1e-3) / 1e12
@@ -279,6 +290,9 @@ def run_linear(args, w):
                     "fused_query_p50_ms": fused["query_p50_ms"] if fused else None,
                     "fused_query_p99_ms": fused["query_p99_ms"] if fused else None},
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "ntts_per_s": {"forward": round(Q * d * 2 * L / (phases["query_ntt"] * 1e-3), 1),
+                       "inverse": round(Q * C * 2 * L / (phases["intt_mask"] * 1e-3), 1),
+                       "N": N},
         "roofline": roofline if Q > 1 or not fused else fused["roofline"],
         "cpu_baseline": cpu,
     }
@@ -367,8 +381,14 @@ def run_clustered(args):
     cout, cshare = srv.center_distances(ct, qids)
     selected = select((cout, cshare, queries))
     work = srv.work_list(selected)
+    # phase 2's per-query chunk lists get their own tuned schedule (register
+    # tile or persistent shape); phase 1 keeps the default all-pairs one
+    from paper_1904_02033_amd import autotune
+    best2, timed2 = autotune.tune(ctx, srv.db, ct, srv.key_points, qids, work=work, reps=2)
+    log(f"phase-2 autotune: {best2.label()} " +
+        ", ".join(f"{c.label()} {c.ms:.2f}" for c in sorted(timed2, key=lambda c: c.ms)))
     D1 = stage.Distances(ctx, srv.cdb, Q, mode=nat.SANNS_MODE_BATCHED)
-    D2 = stage.Distances(ctx, srv.db, Q, work=work, mode=nat.SANNS_MODE_BATCHED)
+    D2 = stage.Distances(ctx, srv.db, Q, work=work, mode=best2.mode)
     for _ in range(args.warmup):
         D1.run(ct, srv.key_centers, qids)
         D2.run(ct, srv.key_points, qids)
@@ -412,7 +432,10 @@ def run_clustered(args):
         "config": {"workload": f"clustered: {len(cdb.points):,} x {w.d} int8, "
                                f"{srv.n_clusters} Zipf clusters + {cdb.stash_size:,} stash, "
                                f"{Q} queries x {u} clusters, N={ctx.N}, L={ctx.L}, t={ctx.t}",
-                   "chunks": srv.db.n_chunks, "centre_chunks": srv.cdb.n_chunks},
+                   "chunks": srv.db.n_chunks, "centre_chunks": srv.cdb.n_chunks,
+                   "phase2_form": best2.label(),
+                   "phase2_schedules_ms": {c.label(): round(c.ms, 3)
+                                           for c in sorted(timed2, key=lambda c: c.ms)}},
         "requested_pairs_per_step": int(req_pairs),
         "slots_processed_per_step": int(slots),
         "phase1_ms_p50": round(pct(p1, 50), 3), "phase2_ms_p50": round(pct(p2, 50), 3),
