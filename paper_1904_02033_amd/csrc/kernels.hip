@@ -364,14 +364,24 @@ __device__ __forceinline__ void mac_reg_slot(const MacTile<QT, CT>& T, int s, in
     }
 }
 
+// Flat grid of (tile, slot range, limb) blocks, tile fastest, dealt to the
+// XCDs in contiguous ranges (blocks are dispatched to XCDs round-robin): the
+// consecutive tiles of one query group then run on one XCD at the same slot
+// range, so that group's query operands are reused from that XCD's L2.
 template <int QT, int CT>
 __global__ void __launch_bounds__(256)
 k_mac(const uint2* __restrict__ qntt, const uint2* __restrict__ db,
-      const MacTile<QT, CT>* __restrict__ tiles, int Q, int d, int L, int logN, int C,
-      PrimeSet ps, uint64_t* __restrict__ out) {
-  const MacTile<QT, CT> T = tiles ? tiles[blockIdx.y] : regular_tile<QT, CT>(blockIdx.y, Q, C);
-  mac_reg_slot<QT, CT>(T, blockIdx.x * blockDim.x + threadIdx.x, blockIdx.z, qntt, db, d, L,
-                       1 << logN, C, ps, out);
+      const MacTile<QT, CT>* __restrict__ tiles, int n_tiles, int Q, int d, int L, int logN,
+      int C, int n_blocks, PrimeSet ps, uint64_t* __restrict__ out) {
+  const int per_xcd = (n_blocks + 7) >> 3;
+  const int lin = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (lin >= n_blocks) return;
+  const int y = lin % n_tiles, rest = lin / n_tiles;
+  const int nsr = (1 << logN) / blockDim.x;
+  const int sr = rest % nsr, l = rest / nsr;
+  const MacTile<QT, CT> T = tiles ? tiles[y] : regular_tile<QT, CT>(y, Q, C);
+  mac_reg_slot<QT, CT>(T, sr * blockDim.x + threadIdx.x, l, qntt, db, d, L, 1 << logN, C, ps,
+                       out);
 }
 
 // LDS-staged multiply-accumulate for the every-query-against-every-chunk
@@ -1294,9 +1304,10 @@ static hipError_t launch_mac_t(const uint2* qntt, const uint2* db, const void* t
                                const PrimeSet& ps, uint64_t* out, hipStream_t st) {
   const int N = 1 << logN;
   const int bs = N < 256 ? N : 256;
-  dim3 grid(N / bs, n_tiles, L);
-  hipLaunchKernelGGL((k_mac<QT, CT>), grid, dim3(bs), 0, st, qntt, db,
-                     (const MacTile<QT, CT>*)tiles, Q, d, L, logN, C, ps, out);
+  const long nb = (long)(N / bs) * n_tiles * L;
+  const long per_xcd = (nb + 7) >> 3;
+  hipLaunchKernelGGL((k_mac<QT, CT>), dim3((unsigned)(per_xcd * 8)), dim3(bs), 0, st, qntt, db,
+                     (const MacTile<QT, CT>*)tiles, n_tiles, Q, d, L, logN, C, (int)nb, ps, out);
   return hipGetLastError();
 }
 
