@@ -140,7 +140,7 @@ void choose_shape(const sanns_ctx* ctx, uint32_t Q, bool regular, int& qt, int& 
     ct = ctx->force_ct;
   } else if (Q <= 1) {
     qt = 1;
-    ct = 4;
+    ct = 8;  // fastest for one query at 1M x 128 (0.59 ms vs 0.63 ms for 1 x 4)
   } else {
     qt = 2;
     ct = 4;
