@@ -128,8 +128,10 @@ sanns_status check_params(const sanns_params* p) {
 
 // Choose the multiply-accumulate kernel: an LDS-staged variant (lds > 0)
 // for a batch of at least two queries against every chunk, otherwise the
-// (queries x chunks) register tile qt x ct.
-void choose_shape(const sanns_ctx* ctx, uint32_t Q, bool regular, int& qt, int& ct, int& lds) {
+// (queries x chunks) register tile qt x ct.  q_per_chunk: mean number of
+// queries per chunk of a work list.
+void choose_shape(const sanns_ctx* ctx, uint32_t Q, bool regular, double q_per_chunk, int& qt,
+                  int& ct, int& lds) {
   lds = 0;
   if (regular && Q >= 2) {
     lds = ctx->force_lds > 0 ? ctx->force_lds : kDefaultLdsVariant;
@@ -138,9 +140,11 @@ void choose_shape(const sanns_ctx* ctx, uint32_t Q, bool regular, int& qt, int& 
   if (ctx->force_qt > 0) {
     qt = ctx->force_qt;
     ct = ctx->force_ct;
-  } else if (Q <= 1) {
+  } else if (Q <= 1 || (!regular && q_per_chunk < 2.0)) {
+    // one query, or work lists whose chunks are mostly scanned by a single
+    // query (the clustered form's cluster chunks): 1 x 8 measured fastest
     qt = 1;
-    ct = 8;  // fastest for one query at 1M x 128 (0.59 ms vs 0.63 ms for 1 x 4)
+    ct = 8;
   } else {
     qt = 2;
     ct = 4;
@@ -653,7 +657,18 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
   }
 
   int qt, ct, lds;
-  choose_shape(ctx, Q, work == nullptr, qt, ct, lds);
+  double q_per_chunk = Q;
+  if (work) {
+    std::vector<char> seen(C, 0);
+    uint32_t distinct = 0;
+    for (uint32_t m = 0; m < M; ++m)
+      if (!seen[work[2 * m + 1]]) {
+        seen[work[2 * m + 1]] = 1;
+        ++distinct;
+      }
+    q_per_chunk = (double)M / (distinct ? distinct : 1);
+  }
+  choose_shape(ctx, Q, work == nullptr, q_per_chunk, qt, ct, lds);
   if (pshape) {
     qt = kPersistTileQ;
     ct = kPersistTileC;
