@@ -695,7 +695,13 @@ __device__ __forceinline__ void mac_dl_tile(int lin, int tid, uint4* sq0, uint4*
 #pragma unroll
         for (int b = 0; b < CT; ++b) res[a][c][b] = 0;
   }
+  // Threads whose whole chunk group lies past the last chunk (the padding of
+  // a ragged final chunk tile) still stage loads and meet the barriers but
+  // skip the multiply-adds; the group is uniform over a wavefront when
+  // S QG is a multiple of 64, so those waves free their ALU slots.
+  const bool idle = k0 + gc * CT >= C;
   auto compute = [&](const uint4* bq4, const uint4* bd4, int ndi) {
+    if (idle) return;
     const uint2* bq = reinterpret_cast<const uint2*>(bq4);
     const uint2* bd = reinterpret_cast<const uint2*>(bd4);
 #pragma unroll UNR
