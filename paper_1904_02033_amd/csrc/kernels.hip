@@ -55,7 +55,7 @@ __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
     bad |= v[a] >= P.q;
   }
   if (bad && err) atomicOr(err, 1u);
-  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P.q);
+  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P);
   uint64_t* dst = out + (size_t)p * N;
   if (split) {
     uint2* dst2 = reinterpret_cast<uint2*>(dst);
@@ -1003,7 +1003,7 @@ k_encode_ntt(const int16_t* __restrict__ gt, uint2* __restrict__ dbres, int k0, 
     const int x = src[coef_index<LOGN>(tid, a)];
     v[a] = x < 0 ? P.q - (uint64_t)(-x) : (uint64_t)x;
   }
-  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P.q);
+  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P);
   uint2* dst = dbres + (size_t)b * N;
 #pragma unroll
   for (int a = 0; a < 16; ++a) {
@@ -1031,7 +1031,7 @@ k_sk_ntt(const int8_t* __restrict__ sk, uint64_t* __restrict__ out, PrimeSet ps,
     const int x = sk[coef_index<LOGN>(tid, a)];
     v[a] = x < 0 ? P.q - (uint64_t)(-x) : (uint64_t)x;
   }
-  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P.q);
+  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P);
 #pragma unroll
   for (int a = 0; a < 16; ++a) out[(size_t)l * N + ntt_slot<LOGN>(tid, a)] = v[a];
 }
@@ -1053,7 +1053,7 @@ k_encrypt(const uint64_t* __restrict__ a_in, const int16_t* __restrict__ e_in,
   uint64_t v[16];
 #pragma unroll
   for (int x = 0; x < 16; ++x) v[x] = a[coef_index<LOGN>(tid, x)];
-  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P.q);
+  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P);
 #pragma unroll
   for (int x = 0; x < 16; ++x)
     v[x] = mulmod(v[x], sk_ntt[(size_t)l * N + ntt_slot<LOGN>(tid, x)], P);
@@ -1172,7 +1172,7 @@ k_decrypt(const uint64_t* __restrict__ ct, const uint64_t* __restrict__ sk_ntt,
     uint64_t v[16];
 #pragma unroll
     for (int a = 0; a < 16; ++a) v[a] = c1[coef_index<LOGN>(tid, a)];
-    ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P.q);
+    ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P);
 #pragma unroll
     for (int a = 0; a < 16; ++a)
       v[a] = mulmod(v[a], sk_ntt[(size_t)l * N + ntt_slot<LOGN>(tid, a)], P);

@@ -9,8 +9,12 @@
 // Inverse: Gentleman-Sande with the Psi^-1 tables; its last stage also
 // multiplies by N^-1 (entry 0 of the inverse table, never a stage twiddle,
 // holds Psi^-1_rev[1] N^-1).
-// Lazy reduction (Harvey) with the estimated Shoup quotient (products in
-// [0, 4q)): forward values stay in [0, 8q), inverse values in [0, 4q).
+// Lazy reduction with the estimated Shoup quotient (products in [0, 4q) for
+// any input below 2^63).  Forward: no reduction inside the transform -- each
+// butterfly maps values below B q to values below (B + 4) q (X + T and
+// X + 4q - T), so after log2 N <= 14 stages they stay below 57 q < 2^60 -- and
+// one reduction at the end.  Inverse: the sum path doubles per stage, so sums
+// are brought back to [0, 4q) at every stage (Harvey).
 //
 // Stages are grouped in passes of up to four index bits; the narrow pass (if
 // log2 N is not a multiple of four) is the forward's first and the inverse's
@@ -79,7 +83,7 @@ __device__ __forceinline__ const u64x2* tw_stage(const u64x2* tw, int tid, int p
   return tw + b;
 }
 
-template <int LOGN, int B, int LO, bool FIRST>
+template <int LOGN, int B, int LO>
 __device__ __forceinline__ void fwd_pass(uint64_t (&v)[16], int tid,
                                          const u64x2* __restrict__ tw, uint64_t q) {
   const uint64_t q4 = 4 * q, nq = 0 - q;
@@ -96,9 +100,7 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&v)[16], int tid,
 #pragma unroll
         for (int l = 0; l < (1 << rp); ++l) {
           const int a = a0 | l, b = a | (1 << rp);
-          uint64_t X = v[a];
-          // inputs of the very first stage are already below q
-          if (!(FIRST && rp == B - 1)) X = csub(X, q4);
+          const uint64_t X = v[a];
           const uint64_t Tm = shoup_approx(v[b], W.x, W.y, nq);
           v[a] = X + Tm;
           v[b] = (X + q4) - Tm;
@@ -160,7 +162,7 @@ __device__ __forceinline__ void fwd_from(uint64_t (&v)[16], uint64_t* lds, int t
                                          const u64x2* __restrict__ tw, uint64_t q) {
   using S = NttShape<LOGN>;
   constexpr int LO = S::fwd_lo(J), B = S::fwd_b(J);
-  fwd_pass<LOGN, B, LO, J == 0>(v, tid, tw, q);
+  fwd_pass<LOGN, B, LO>(v, tid, tw, q);
   if constexpr (J + 1 < S::P) {
     // Within later passes a thread stores exactly the positions it loaded,
     // so one barrier before the first store (guarding LDS still read by an
@@ -193,10 +195,13 @@ __device__ __forceinline__ void inv_from(uint64_t (&v)[16], uint64_t* lds, int t
 // lds holds NttShape<LOGN>::lds_bytes; the caller synchronises before reusing it.
 template <int LOGN>
 __device__ __forceinline__ void ntt_fwd(uint64_t (&v)[16], uint64_t* lds, int tid,
-                                        const u64x2* __restrict__ tw, uint64_t q) {
-  fwd_from<LOGN, 0>(v, lds, tid, tw, q);
+                                        const u64x2* __restrict__ tw, const Prime& P) {
+  static_assert(LOGN <= 14, "forward values must stay below 2^60");
+  fwd_from<LOGN, 0>(v, lds, tid, tw, P.q);
+  const uint64_t nq = 0 - P.q;
 #pragma unroll
-  for (int a = 0; a < 16; ++a) v[a] = csub(csub(csub(v[a], 4 * q), 2 * q), q);
+  for (int a = 0; a < 16; ++a)
+    v[a] = csub(csub(shoup_approx(v[a], 1, P.one, nq), 2 * P.q), P.q);
 }
 
 // Inverse transform times N^-1.  Input: residues below q, slot a = evaluation
