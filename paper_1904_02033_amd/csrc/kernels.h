@@ -24,8 +24,9 @@ struct DecodeConst {
   int words;                           // words used by q and the sums
 };
 
-// Twiddle tables of one limb: N (psi_rev, psi_rev') pairs, then N
-// (ipsi_rev, ipsi_rev') pairs whose entry 0 holds ipsi_rev[1] N^-1.
+// Twiddle tables of one limb (pairs of value and Shoup companion): N forward
+// pairs psi_rev, then N inverse stage pairs (entry 2^p + m = omega^-(m N /
+// 2^(p+1)), entry 0 unused), then N final factors psi^-j N^-1.
 struct TwSet {
   const u64x2* tw[kMaxLimbs];
 };

@@ -6,15 +6,18 @@
 // Forward: merged-psi Cooley-Tukey (bit-reversed output), the butterfly at
 // stride 2^p between indices j and j + 2^p uses Psi_rev[(N + j) >> (p + 1)],
 // Psi_rev[m] = psi^bitrev(m) with psi a primitive 2N-th root of unity mod q.
-// Inverse: Gentleman-Sande with the Psi^-1 tables; its last stage also
-// multiplies by N^-1 (entry 0 of the inverse table, never a stage twiddle,
-// holds Psi^-1_rev[1] N^-1).
+// The forward output at position k is the cyclic transform of (psi^j a_j) at
+// frequency bitrev(k), so the inverse is a decimation-in-time Cooley-Tukey
+// transform of that bit-reversed input with omega^-1 = psi^-2 (natural-order
+// output), followed by the factor psi^-j N^-1 per coefficient: the butterfly
+// at stride 2^p uses W_inv[2^p + (j mod 2^p)] = omega^-((j mod 2^p) N / 2^(p+1))
+// (stage 0 multiplies by 1).
 // Lazy reduction with the estimated Shoup quotient (products in [0, 4q) for
-// any input below 2^63).  Forward: no reduction inside the transform -- each
+// any input below 2^63): no reduction inside either transform -- each
 // butterfly maps values below B q to values below (B + 4) q (X + T and
-// X + 4q - T), so after log2 N <= 14 stages they stay below 57 q < 2^60 -- and
-// one reduction at the end.  Inverse: the sum path doubles per stage, so sums
-// are brought back to [0, 4q) at every stage (Harvey).
+// X + 4q - T; the inverse's twiddle-free stage 0 maps inputs below q to
+// values below 3q), so after log2 N <= 14 stages they stay below 58 q < 2^60
+// -- and one reduction at the end.
 //
 // Stages are grouped in passes of up to four index bits; the narrow pass (if
 // log2 N is not a multiple of four) is the forward's first and the inverse's
@@ -110,33 +113,43 @@ __device__ __forceinline__ void fwd_pass(uint64_t (&v)[16], int tid,
   }
 }
 
-template <int LOGN, int B, int LO, bool FIRST, bool LAST>
+// Twiddle base of inverse stage p: index 2^p + (j mod 2^p), j = eidx(tid, x),
+// is (2^p + (eidx(tid, 0) mod 2^p)) + (eidx(0, x) mod 2^p).  Only in the pass
+// over the lowest bits does j mod 2^p not involve the thread id.
+template <int LOGN, int B, int LO>
+__device__ __forceinline__ const u64x2* tw_inv_stage(const u64x2* tw, int tid, int p) {
+  int b = (1 << p) + (eidx<LOGN, B, LO>(tid, 0) & ((1 << p) - 1));
+  if (LO == 0) b = __builtin_amdgcn_readfirstlane(b);
+  return tw + b;
+}
+
+template <int LOGN, int B, int LO>
 __device__ __forceinline__ void inv_pass(uint64_t (&v)[16], int tid,
-                                         const u64x2* __restrict__ tw, const Prime& P) {
-  const uint64_t q4 = 4 * P.q, nq = 0 - P.q;
+                                         const u64x2* __restrict__ tw, uint64_t q) {
+  const uint64_t q2 = 2 * q, q4 = 4 * q, nq = 0 - q;
 #pragma unroll
   for (int rp = 0; rp < B; ++rp) {
     const int p = LO + rp;
-    const bool merged = LAST && rp == B - 1;  // the stage that also scales by N^-1
-    const u64x2* tb = tw_stage<LOGN, B, LO>(tw, tid, p + 1);
+    const u64x2* tb = tw_inv_stage<LOGN, B, LO>(tw, tid, p);
 #pragma unroll
     for (int e = 0; e < (16 >> B); ++e) {
 #pragma unroll
       for (int g = 0; g < (1 << (B - 1 - rp)); ++g) {
         const int a0 = (e << B) | (g << (rp + 1));
-        const u64x2 W = merged ? tw[0] : tb[eidx<LOGN, B, LO>(0, a0) >> (p + 1)];
 #pragma unroll
         for (int l = 0; l < (1 << rp); ++l) {
           const int a = a0 | l, b = a | (1 << rp);
           const uint64_t X = v[a], Y = v[b];
-          uint64_t s = X + Y;
-          if (merged) {
-            s = shoup_approx(s, P.ninv, P.ninvp, nq);
-          } else if (!(FIRST && rp == 0)) {
-            s = csub(s, q4);  // first-stage inputs are below q, their sum below 2q
+          if (p == 0) {
+            // twiddle 1; inputs are below q
+            v[a] = X + Y;
+            v[b] = (X + q2) - Y;
+          } else {
+            const u64x2 W = tb[eidx<LOGN, B, LO>(0, a) & ((1 << p) - 1)];
+            const uint64_t Tm = shoup_approx(Y, W.x, W.y, nq);
+            v[a] = X + Tm;
+            v[b] = (X + q4) - Tm;
           }
-          v[a] = s;
-          v[b] = shoup_approx((X + q4) - Y, W.x, W.y, nq);
         }
       }
     }
@@ -180,7 +193,7 @@ __device__ __forceinline__ void inv_from(uint64_t (&v)[16], uint64_t* lds, int t
                                          const u64x2* __restrict__ tw, const Prime& P) {
   using S = NttShape<LOGN>;
   constexpr int LO = S::inv_lo(J), B = S::inv_b(J);
-  inv_pass<LOGN, B, LO, J == 0, J + 1 == S::P>(v, tid, tw, P);
+  inv_pass<LOGN, B, LO>(v, tid, tw, P.q);
   if constexpr (J + 1 < S::P) {
     if (J == 0) __syncthreads();
     lds_store<LOGN, B, LO>(v, lds, tid);
@@ -204,15 +217,23 @@ __device__ __forceinline__ void ntt_fwd(uint64_t (&v)[16], uint64_t* lds, int ti
     v[a] = csub(csub(shoup_approx(v[a], 1, P.one, nq), 2 * P.q), P.q);
 }
 
-// Inverse transform times N^-1.  Input: residues below q, slot a = evaluation
-// a + 16 tid (the forward's output order).  Output: slot a = coefficient
-// coef_index(tid, a) in [0, q).  tw points at the limb's inverse table.
+// Inverse transform.  Input: residues below q, slot a = evaluation a + 16 tid
+// (the forward's output order).  Output: slot a = coefficient
+// coef_index(tid, a) in [0, q).  tw points at the limb's inverse stage table,
+// which is followed by the N (psi^-j N^-1, companion) pairs of the final
+// factor.
 template <int LOGN>
 __device__ __forceinline__ void ntt_inv(uint64_t (&v)[16], uint64_t* lds, int tid,
                                         const u64x2* __restrict__ tw, const Prime& P) {
+  static_assert(LOGN <= 14, "inverse values must stay below 2^60");
   inv_from<LOGN, 0>(v, lds, tid, tw, P);
+  const u64x2* F = tw + NttShape<LOGN>::N;
+  const uint64_t nq = 0 - P.q;
 #pragma unroll
-  for (int a = 0; a < 16; ++a) v[a] = csub(csub(v[a], 2 * P.q), P.q);
+  for (int a = 0; a < 16; ++a) {
+    const u64x2 f = F[coef_index<LOGN>(tid, a)];
+    v[a] = csub(csub(shoup_approx(v[a], f.x, f.y, nq), 2 * P.q), P.q);
+  }
 }
 
 }  // namespace sanns

@@ -104,25 +104,36 @@ std::vector<uint64_t> twiddle_table(uint32_t N, uint64_t q, uint64_t psi) {
   int logN = 0;
   while ((1u << logN) < N) ++logN;
   const uint64_t ipsi = powmod(psi, q - 2, q);
-  std::vector<uint64_t> pw(N), ipw(N);
-  pw[0] = ipw[0] = 1;
+  const uint64_t iw = mulmod(ipsi, ipsi, q);  // omega^-1, omega = psi^2
+  const uint64_t ninv = powmod(N % q, q - 2, q);
+  std::vector<uint64_t> pw(N), iww(N);
+  pw[0] = iww[0] = 1;
   for (uint32_t i = 1; i < N; ++i) {
     pw[i] = mulmod(pw[i - 1], psi, q);
-    ipw[i] = mulmod(ipw[i - 1], ipsi, q);
+    iww[i] = mulmod(iww[i - 1], iw, q);
   }
-  // [0, 2N): forward pairs; [2N, 4N): inverse pairs
-  std::vector<uint64_t> t(4 * (size_t)N);
+  // [0, 2N): forward (Psi_rev, companion) pairs;
+  // [2N, 4N): inverse stage pairs, entry 2^p + m = omega^-(m N / 2^(p+1));
+  // [4N, 6N): final factor psi^-j N^-1 pairs in coefficient order.
+  std::vector<uint64_t> t(6 * (size_t)N, 0);
   for (uint32_t m = 0; m < N; ++m) {
     const uint32_t r = bitrev(m, logN);
     t[2 * (size_t)m] = pw[r];
     t[2 * (size_t)m + 1] = shoup_companion(pw[r], q);
-    t[2 * (size_t)N + 2 * m] = ipw[r];
-    t[2 * (size_t)N + 2 * m + 1] = shoup_companion(ipw[r], q);
   }
-  // inverse entry 0 (no stage uses it): the last stage's twiddle times N^-1
-  const uint64_t merged = mulmod(ipw[bitrev(1, logN)], powmod(N % q, q - 2, q), q);
-  t[2 * (size_t)N] = merged;
-  t[2 * (size_t)N + 1] = shoup_companion(merged, q);
+  for (int p = 0; p < logN; ++p)
+    for (uint32_t m = 0; m < (1u << p); ++m) {
+      const uint64_t w = iww[(size_t)m * (N >> (p + 1))];
+      const size_t i = 2 * (size_t)N + 2 * ((1u << p) + m);
+      t[i] = w;
+      t[i + 1] = shoup_companion(w, q);
+    }
+  uint64_t f = ninv;
+  for (uint32_t j = 0; j < N; ++j) {
+    t[4 * (size_t)N + 2 * j] = f;
+    t[4 * (size_t)N + 2 * j + 1] = shoup_companion(f, q);
+    f = mulmod(f, ipsi, q);
+  }
   return t;
 }
 

@@ -312,7 +312,7 @@ extern "C" sanns_status sanns_ctx_create(const sanns_params* p, int device, sann
     return fail(SANNS_E_DEVICE, "context setup: %s", hipGetErrorString(e));
   }
   for (uint32_t l = 0; l < L; ++l)
-    ctx->tws.tw[l] = reinterpret_cast<const u64x2*>(ctx->d_tw + (size_t)l * 4 * N);
+    ctx->tws.tw[l] = reinterpret_cast<const u64x2*>(ctx->d_tw + (size_t)l * 6 * N);
   *out = ctx;
   return SANNS_OK;
 }
