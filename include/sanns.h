@@ -55,6 +55,12 @@ typedef enum {
 /* Parameter flags. */
 #define SANNS_FLAG_INSECURE_TEST 1u /* allow N < 1024 or log2 q above the
                                        128-bit cap (tests only)            */
+#define SANNS_FLAG_DIGIT_DB 2u      /* databases of dimension d <= 128 (and
+                                       N >= 64) also hold their int8 digit
+                                       form, which the matrix-core schedule
+                                       SANNS_SCHEDULE_MFMA reads; it becomes
+                                       the default schedule of all-pairs
+                                       batches of two or more queries      */
 
 /* BFV parameters (Section 2.3; Section 5 "Parameters").
  *   N    ring degree, power of two, 16 <= N <= 16384
@@ -88,7 +94,12 @@ typedef struct sanns_ctx sanns_ctx;
  *   residues [L][n_chunks][d][N] of 8 bytes: the NTT form of g_{i,k} mod q_l,
  *            stored as two 27-bit halves (low half in the first 32-bit word);
  *   norms    [n_chunks][N] uint32: ||p||^2 of the point in each slot (0 for
- *            padding slots).
+ *            padding slots);
+ *   digits   (contexts created with SANNS_FLAG_DIGIT_DB, d <= 128 only)
+ *            [L][N][n_chunks][7 Dp + 16] int8, Dp = d rounded up to 64: the
+ *            same residues x as seven signed base-256 digits x_a in
+ *            [-128, 127] (x = sum_a x_a 256^a), digit rows of Dp bytes
+ *            indexed by coordinate, zero past d, then 16 padding bytes.
  * Size: sanns_db_bytes(). */
 typedef struct {
     void *mem;
@@ -254,14 +265,18 @@ sanns_status sanns_device_status(sanns_ctx *ctx, void *stream);
 /* Fix the multiply-accumulate schedule (used by the autotuner):
  *   lds_variant  LDS-staged kernel used for batches of >= 2 queries against
  *                every chunk (work == NULL): 1..11 (register-staged) or 21..27
- *                (direct-to-LDS staged), or 0 for the default; or the tile
- *                shape of SANNS_MODE_PERSISTENT: 41..44 (N = 8192), 51..52
- *                (N = 4096), 61 (N = 2048), 71 (N = 16384);
+ *                (direct-to-LDS staged), SANNS_SCHEDULE_MFMA (int8 matrix
+ *                cores on the digit form; the context needs
+ *                SANNS_FLAG_DIGIT_DB and sanns_distances then needs d <= 128),
+ *                or 0 for the default; or the tile shape of
+ *                SANNS_MODE_PERSISTENT: 41..44 (N = 8192), 51..52 (N = 4096),
+ *                61 (N = 2048), 71 (N = 16384);
  *   qt x ct      register tile (queries x chunks per thread) used for every
  *                other call: 1x1, 1x2, 1x4, 1x8, 2x2, 2x4, 4x2, 2x3, 3x2, or
  *                0x0 for the automatic choice.
  * Outputs do not depend on the schedule.  Errors: SANNS_E_INVALID for a
  * variant or shape that is not built. */
+#define SANNS_SCHEDULE_MFMA 81
 sanns_status sanns_set_schedule(sanns_ctx *ctx, int lds_variant, int qt, int ct);
 
 /* Phases timed by the profiler, in launch order. */

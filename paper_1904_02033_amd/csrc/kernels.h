@@ -31,6 +31,20 @@ struct TwSet {
   const u64x2* tw[kMaxLimbs];
 };
 
+// Constants of the exact fold of the int8 matrix-core digit sums of one limb:
+// a sum V = g0 + g1 2^32 + h 2^64 of signed 64-bit parts is reduced as
+// (g0 + offa) + [ (g1 + offa) 2^32 ] + [ (h + offb) 2^64 ]  (mod q).
+struct DigitConst {
+  uint64_t w32, w32p;  // 2^32 mod q and its Shoup companion
+  uint64_t w64, w64p;  // 2^64 mod q and its Shoup companion
+  uint64_t offa;       // smallest multiple of q >= 2^53
+  uint64_t offb;       // smallest multiple of q >= 2^57
+};
+
+struct DigitSet {
+  DigitConst c[kMaxLimbs];
+};
+
 struct MaskKey {
   uint32_t k[8];
 };

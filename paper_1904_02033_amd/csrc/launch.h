@@ -77,6 +77,24 @@ int persistent_max_d(int shape);          // largest d the shape accumulates in 
 hipError_t launch_persistent(int shape, const PersistArgs& A, const PrimeSet& ps,
                              const TwSet& tws, hipStream_t st);
 
+// Matrix-core schedule of the all-pairs multiply-accumulate (mfma.hip).
+constexpr int kMfmaSchedule = 81;  // schedule id of sanns_set_schedule
+constexpr int kMfmaMaxD = 128;     // largest d (two MFMA steps of 64 coordinates)
+bool mfma_supported(int logN, int d);
+int mfma_padded_d(int d);   // d rounded up to 64
+int mfma_db_stride(int d);  // bytes per (limb, slot, chunk) of the database digits
+// Query NTT form [Q][d][2][L][N] uint64 -> query digits [L][N][2Q][7][Dp].
+hipError_t launch_query_digits(const uint64_t* qntt, int8_t* qd, int Q, int d, int L, int logN,
+                               hipStream_t st);
+// Database residues [L][C][d][N] (halves) -> database digits [L][N][C][Sk].
+hipError_t launch_db_digits(const uint2* dbres, int8_t* dbd, int C, int d, int L, int logN,
+                            hipStream_t st);
+// All-pairs sums into the slot-major buffer `sums` [L][N][2Q][C], then
+// transposed into ct_out [Q C][2][L][N] (NTT form, residues in [0, q)).
+hipError_t launch_mac_mfma(const int8_t* qd, const int8_t* dbd, int Q, int d, int C, int L,
+                           int logN, const PrimeSet& ps, const DigitSet& ds, uint64_t* sums,
+                           uint64_t* ct_out, hipStream_t st);
+
 hipError_t launch_gather(const void* pts, int is_signed, long n, int d,
                          const int64_t* slot_point, long base, long total, int logN,
                          int16_t* gt, uint32_t* norms, uint32_t* err, hipStream_t st);

@@ -150,6 +150,17 @@ Prime prime_consts(uint32_t N, uint64_t q, uint64_t delta_mod_q) {
   return P;
 }
 
+DigitConst digit_consts(uint64_t q) {
+  DigitConst D;
+  D.w32 = (uint64_t)((((u128)1) << 32) % q);
+  D.w32p = shoup_companion(D.w32, q);
+  D.w64 = (uint64_t)((((u128)1) << 64) % q);
+  D.w64p = shoup_companion(D.w64, q);
+  D.offa = (((1ull << 53) + q - 1) / q) * q;
+  D.offb = (((1ull << 57) + q - 1) / q) * q;
+  return D;
+}
+
 // floor(Q/t) = (Q - (Q mod t)) / t  and  Q = 0 mod q_l, so
 // floor(Q/t) = -(Q mod t) t^-1  (mod q_l).
 std::vector<uint64_t> delta_mod_limbs(const std::vector<uint64_t>& qs, uint64_t t) {

@@ -25,6 +25,7 @@ uint64_t min_primitive_root_2n(uint32_t N, uint64_t q);
 std::vector<uint64_t> twiddle_table(uint32_t N, uint64_t q, uint64_t psi);
 
 Prime prime_consts(uint32_t N, uint64_t q, uint64_t delta_mod_q);
+DigitConst digit_consts(uint64_t q);
 
 // Delta = floor(Q / t) mod q_l for every limb, Q = prod q_l.
 std::vector<uint64_t> delta_mod_limbs(const std::vector<uint64_t>& qs, uint64_t t);

@@ -62,6 +62,8 @@ struct sanns_ctx {
   int device = 0;
   int logN = 0;
   PrimeSet ps{};
+  DigitSet ds{};
+  bool digit_db = false;  // databases carry the int8 digit form (SANNS_FLAG_DIGIT_DB)
   TwSet tws{};
   DecodeConst dec{};
   uint64_t tone = 0;  // floor(2^64 / t)
@@ -130,12 +132,20 @@ sanns_status check_params(const sanns_params* p) {
 // for a batch of at least two queries against every chunk, otherwise the
 // (queries x chunks) register tile qt x ct.  q_per_chunk: mean number of
 // queries per chunk of a work list.
-void choose_shape(const sanns_ctx* ctx, uint32_t Q, bool regular, double q_per_chunk, int& qt,
-                  int& ct, int& lds) {
+bool db_has_digits(const sanns_ctx* ctx, uint32_t d) {
+  return ctx->digit_db && mfma_supported(ctx->logN, (int)d);
+}
+
+void choose_shape(const sanns_ctx* ctx, uint32_t Q, uint32_t d, bool regular, double q_per_chunk,
+                  int& qt, int& ct, int& lds) {
   lds = 0;
   if (regular && Q >= 2) {
-    lds = ctx->force_lds > 0 ? ctx->force_lds : kDefaultLdsVariant;
-    if ((int)ctx->p.N % mac_lds_min_n(lds) != 0) lds = 0;
+    if (ctx->force_lds > 0)
+      lds = ctx->force_lds;
+    else
+      lds = db_has_digits(ctx, d) ? kMfmaSchedule : kDefaultLdsVariant;
+    if (lds == kMfmaSchedule && !db_has_digits(ctx, d)) lds = kDefaultLdsVariant;
+    if (lds != kMfmaSchedule && (int)ctx->p.N % mac_lds_min_n(lds) != 0) lds = 0;
   }
   if (ctx->force_qt > 0) {
     qt = ctx->force_qt;
@@ -217,7 +227,7 @@ sanns_status stage_upload(sanns_ctx* ctx, void* dst, const void* src, size_t byt
 }
 
 struct WsLayout {
-  size_t qntt, tiles, work, tmp, ctrl, total;
+  size_t qntt, tiles, work, tmp, ctrl, qdig, sums, total;
 };
 
 WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M) {
@@ -234,6 +244,13 @@ WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M) {
   off += align256(2 * L * N * 8);
   w.ctrl = off;  // control words of the persistent schedule
   off += align256(kPersistCtrlWords * sizeof(uint32_t));
+  w.qdig = w.sums = off;
+  if (ctx->digit_db && mfma_supported(ctx->logN, (int)d)) {
+    // matrix-core schedule: query digits and slot-major sums (2Q rows x C = 2M)
+    off += align256(L * N * 2 * Q * 7 * (size_t)mfma_padded_d((int)d));
+    w.sums = off;
+    off += align256(L * N * 2 * (size_t)M * 8);
+  }
   w.total = off;
   return w;
 }
@@ -278,6 +295,7 @@ extern "C" sanns_status sanns_ctx_create(const sanns_params* p, int device, sann
   ctx->p = *p;
   ctx->device = device;
   ctx->logN = log2u(p->N);
+  ctx->digit_db = (p->flags & SANNS_FLAG_DIGIT_DB) != 0;
   const uint32_t N = p->N, L = p->L;
   std::vector<uint64_t> qs(p->q, p->q + L);
   const auto deltas = host::delta_mod_limbs(qs, p->t);
@@ -285,6 +303,7 @@ extern "C" sanns_status sanns_ctx_create(const sanns_params* p, int device, sann
   try {
     for (uint32_t l = 0; l < L; ++l) {
       ctx->ps.p[l] = host::prime_consts(N, qs[l], deltas[l]);
+      ctx->ds.c[l] = host::digit_consts(qs[l]);
       const uint64_t psi = host::min_primitive_root_2n(N, qs[l]);
       const auto tw = host::twiddle_table(N, qs[l], psi);
       tw_all.insert(tw_all.end(), tw.begin(), tw.end());
@@ -393,8 +412,12 @@ extern "C" sanns_status sanns_set_schedule(sanns_ctx* ctx, int lds_variant, int 
   if (persist && persistent_logn(lds_variant) != ctx->logN)
     return fail(SANNS_E_INVALID, "persistent shape %d is built for N = %d", lds_variant,
                 1 << persistent_logn(lds_variant));
-  if (lds_variant < 0 || (lds_variant > 0 && !persist && mac_lds_min_n(lds_variant) == 0))
+  if (lds_variant < 0 || (lds_variant > 0 && !persist && lds_variant != kMfmaSchedule &&
+                          mac_lds_min_n(lds_variant) == 0))
     return fail(SANNS_E_INVALID, "LDS variant %d is not built", lds_variant);
+  if (lds_variant == kMfmaSchedule && !ctx->digit_db)
+    return fail(SANNS_E_INVALID, "schedule %d needs a context with SANNS_FLAG_DIGIT_DB",
+                lds_variant);
   if (!(qt == 0 && ct == 0) && mac_tile_bytes(qt, ct) == 0)
     return fail(SANNS_E_INVALID, "tile %dx%d is not built", qt, ct);
   std::lock_guard<std::mutex> lock(ctx->mu);
@@ -416,7 +439,9 @@ extern "C" sanns_status sanns_set_schedule(sanns_ctx* ctx, int lds_variant, int 
 extern "C" size_t sanns_db_bytes(const sanns_ctx* ctx, uint32_t n_chunks, uint32_t d) {
   if (!ctx) return 0;
   const size_t N = ctx->p.N, L = ctx->p.L;
-  return L * n_chunks * d * N * 8 + (size_t)n_chunks * N * 4;
+  size_t b = L * n_chunks * d * N * 8 + (size_t)n_chunks * N * 4;
+  if (db_has_digits(ctx, d)) b += L * N * n_chunks * (size_t)mfma_db_stride((int)d);
+  return b;
 }
 
 extern "C" sanns_status sanns_encode_db(sanns_ctx* ctx, const void* points, int dtype,
@@ -450,6 +475,10 @@ extern "C" sanns_status sanns_encode_db(sanns_ctx* ctx, const void* points, int 
                               ctx->ps, ctx->tws, st));
   }
   HIP_TRY(hipFreeAsync(gt, st));
+  if (db_has_digits(ctx, d)) {
+    int8_t* dig = (int8_t*)((char*)db->mem + (size_t)L * C * d * N * 8 + (size_t)C * N * 4);
+    HIP_TRY(launch_db_digits(res, dig, (int)C, (int)d, (int)L, ctx->logN, st));
+  }
   return SANNS_OK;
 }
 
@@ -511,9 +540,10 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
                            uint32_t Q, const MaskKey& K, const uint64_t* qids,
                            const uint32_t* dwork, uint32_t M, int qt, int ct, int lds,
                            const void* dtiles, int n_tiles, uint64_t* ct_out,
-                           uint32_t* share, uint64_t* qntt, hipStream_t st,
-                           bool profile = false) {
+                           uint32_t* share, uint64_t* qntt, int8_t* qdig, uint64_t* sums,
+                           hipStream_t st, bool profile = false) {
   const uint32_t N = ctx->p.N, L = ctx->p.L, C = db->n_chunks, d = db->d;
+  const bool mfma = lds == kMfmaSchedule;
   const uint2* res = (const uint2*)db->mem;
   const uint32_t* norms = (const uint32_t*)((const char*)db->mem + (size_t)L * C * d * N * 8);
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
@@ -530,14 +560,20 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
   };
   HIP_TRY(mark(SANNS_PHASE_QUERY_NTT, false));
   HIP_TRY(launch_ntt_fwd(ct_in, qntt, (int)(Q * d * 2 * L), ctx->logN, (int)L, ctx->ps,
-                         ctx->tws, ctx->d_err, 1, st));
+                         ctx->tws, ctx->d_err, mfma ? 0 : 1, st));
+  if (mfma)
+    HIP_TRY(launch_query_digits(qntt, qdig, (int)Q, (int)d, (int)L, ctx->logN, st));
   HIP_TRY(mark(SANNS_PHASE_QUERY_NTT, true));
   HIP_TRY(mark(SANNS_PHASE_MASKS, false));
   HIP_TRY(launch_masks(K, qids, dwork, (int)C, (int)M, ctx->logN, (uint32_t)ctx->p.t, ctx->tone,
                        share, st));
   HIP_TRY(mark(SANNS_PHASE_MASKS, true));
   HIP_TRY(mark(SANNS_PHASE_MAC, false));
-  if (lds > 0)
+  if (mfma) {
+    const int8_t* dig = (const int8_t*)db->mem + (size_t)L * C * d * N * 8 + (size_t)C * N * 4;
+    HIP_TRY(launch_mac_mfma(qdig, dig, (int)Q, (int)d, (int)C, (int)L, ctx->logN, ctx->ps,
+                            ctx->ds, sums, ct_out, st));
+  } else if (lds > 0)
     HIP_TRY(launch_mac_lds(lds, (const uint2*)qntt, res, (int)Q, (int)d, (int)L, ctx->logN,
                            (int)C, ctx->ps, ct_out, st));
   else
@@ -635,6 +671,8 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
   void* dtiles_buf = ws + W.tiles;
   uint32_t* dwork_buf = (uint32_t*)(ws + W.work);
   uint64_t* tmp = (uint64_t*)(ws + W.tmp);
+  int8_t* qdig = (int8_t*)(ws + W.qdig);
+  uint64_t* sums = (uint64_t*)(ws + W.sums);
   MaskKey K;
   for (int i = 0; i < 8; ++i)
     K.k[i] = (uint32_t)mask_key[4 * i] | (uint32_t)mask_key[4 * i + 1] << 8 |
@@ -668,7 +706,11 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
       }
     q_per_chunk = (double)M / (distinct ? distinct : 1);
   }
-  choose_shape(ctx, Q, work == nullptr, q_per_chunk, qt, ct, lds);
+  if (ctx->force_lds == kMfmaSchedule && !work && Q >= 2 && !db_has_digits(ctx, db->d))
+    return fail(SANNS_E_INVALID,
+                "the matrix-core schedule needs SANNS_FLAG_DIGIT_DB, N >= 64 and d <= %d",
+                kMfmaMaxD);
+  choose_shape(ctx, Q, db->d, work == nullptr, q_per_chunk, qt, ct, lds);
   if (pshape) {
     qt = kPersistTileQ;
     ct = kPersistTileC;
@@ -695,7 +737,7 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
   auto enqueue = [&](hipStream_t s, bool profile) -> sanns_status {
     if (!pshape)
       return enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, lds, dtiles,
-                           n_tiles, ct_out, server_share, qntt, s, profile);
+                           n_tiles, ct_out, server_share, qntt, qdig, sums, s, profile);
     PersistArgs A;
     A.ct_in = ct_in;
     A.qntt = qntt;
@@ -723,7 +765,7 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
 
   if (mode == SANNS_MODE_FUSED || (ctx->profiling && !pshape))
     return enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, lds, dtiles,
-                         n_tiles, ct_out, server_share, qntt, st, ctx->profiling);
+                         n_tiles, ct_out, server_share, qntt, qdig, sums, st, ctx->profiling);
 
   // batched and persistent: replay (or capture once) the sequence as a hipGraph
   GraphKey key;

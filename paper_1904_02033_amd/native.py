@@ -28,6 +28,8 @@ STATUS_NAMES = {0: "SANNS_OK", -1: "SANNS_E_INVALID", -2: "SANNS_E_PARAMS",
 SANNS_MAX_LIMBS = 4
 SANNS_MAX_D = 4096
 SANNS_FLAG_INSECURE_TEST = 1
+SANNS_FLAG_DIGIT_DB = 2
+SANNS_SCHEDULE_MFMA = 81
 SANNS_U8, SANNS_I8 = 0, 1
 SANNS_MODE_PLAIN, SANNS_MODE_FUSED, SANNS_MODE_BATCHED, SANNS_MODE_PERSISTENT = 0, 1, 2, 3
 
