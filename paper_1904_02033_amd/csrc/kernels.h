@@ -39,6 +39,7 @@ struct DigitConst {
   uint64_t w64, w64p;  // 2^64 mod q and its Shoup companion
   uint64_t offa;       // smallest multiple of q >= 2^53
   uint64_t offb;       // smallest multiple of q >= 2^57
+  uint64_t nq;         // 2^64 - q
 };
 
 struct DigitSet {

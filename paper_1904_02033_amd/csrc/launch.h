@@ -89,8 +89,10 @@ hipError_t launch_query_digits(const uint64_t* qntt, int8_t* qd, int Q, int d, i
 // Database residues [L][C][d][N] (halves) -> database digits [L][N][C][Sk].
 hipError_t launch_db_digits(const uint2* dbres, int8_t* dbd, int C, int d, int L, int logN,
                             hipStream_t st);
-// All-pairs sums into the slot-major buffer `sums` [L][N][2Q][C], then
-// transposed into ct_out [Q C][2][L][N] (NTT form, residues in [0, q)).
+// All-pairs sums into the slot-major buffer `sums` ([L][N][Rp][Cp] uint64,
+// Rp = 2Q and Cp = C rounded up to 64 and 32; mfma_sums_bytes), then reduced
+// and transposed into ct_out [Q C][2][L][N] (NTT form, residues in [0, q)).
+size_t mfma_sums_bytes(int Q, int C, int L, int logN);
 hipError_t launch_mac_mfma(const int8_t* qd, const int8_t* dbd, int Q, int d, int C, int L,
                            int logN, const PrimeSet& ps, const DigitSet& ds, uint64_t* sums,
                            uint64_t* ct_out, hipStream_t st);

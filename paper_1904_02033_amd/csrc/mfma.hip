@@ -21,7 +21,8 @@
 //   query digits    [L][N][R][7][Dp] int8    R = 2Q rows, row = 2q + c
 //   database digits [L][N][C][Sk] int8       Sk = 7 Dp + 16: digit rows, then
 //                                            16 bytes of padding (LDS banks)
-//   slot-major sums [L][N][R][C] uint64 in [0, q_l)
+//   slot-major sums [L][N][Rp][Cp] uint64 below 2^58, congruent mod q_l (R and
+//                   C padded to whole tiles of 64 rows and 32 chunks)
 // Fragment of one lane (row or column m = lane % 16, group g = lane / 16) at
 // step s: the 16 bytes of one digit row at coordinates 64s + 16g .. + 15.
 #include <hip/hip_runtime.h>
@@ -37,6 +38,9 @@ constexpr int kMfmaRows = 64;    // rows per workgroup: 4 waves x 16
 constexpr int kMfmaChunks = 32;  // chunks per workgroup: 2 MFMA column tiles
 constexpr int kMfmaSlots = 8;    // consecutive slots per workgroup
 constexpr int kDigitSlots = 32;  // slots per workgroup of the digit transposes
+// s_waitcnt immediate (gfx9 encoding): vmcnt <= 7 (bits 3:0 and 15:14),
+// expcnt and lgkmcnt not waited for (7 in bits 6:4, 15 in bits 11:8).
+constexpr int kWaitAllBut7Vmem = 7 | (7 << 4) | (15 << 8);
 
 // The signed digits of x < 2^54 as the bytes of a word (byte 7 is zero).
 __device__ __forceinline__ uint64_t digit_word(uint64_t x) {
@@ -115,13 +119,14 @@ __device__ __forceinline__ int32_t opaque_i32(int32_t x) {
   return x;
 }
 
-// Residue in [0, q) of V = sum_s S_s 256^s (Dp <= 256, so |S_s| < 2^29):
+// A value below 2^58 congruent to V = sum_s S_s 256^s (Dp <= 256, so
+// |S_s| < 2^29); k_sums_to_ct reduces it to [0, q):
 //   g0 = S0 + S1 2^8 + S2 2^16 + S3 2^24          |g0| < 2^53
 //   g1 = S4 + ... + S7 2^24  (weight 2^32)        |g1| < 2^53
 //   h  = S8 + ... + S11 2^24 + S12 2^32  (weight 2^64),  |h| < 2^57
 // and V = g0 + g1 2^32 + h 2^64.
-__device__ __forceinline__ uint64_t fold_digit_sums(const int32_t (&S)[13], const Prime& P,
-                                                    const DigitConst& D, uint64_t nq) {
+__device__ __forceinline__ uint64_t fold_digit_sums(const int32_t (&S)[13],
+                                                    const DigitConst& D) {
   const int32_t k8 = opaque_i32(1 << 8), k16 = opaque_i32(1 << 16), k24 = opaque_i32(1 << 24);
   auto group = [&](int s) {
     int64_t g = (int64_t)S[s];
@@ -135,45 +140,51 @@ __device__ __forceinline__ uint64_t fold_digit_sums(const int32_t (&S)[13], cons
   const uint64_t x0 = (uint64_t)(g0 + (int64_t)D.offa);
   const uint64_t x1 = (uint64_t)(g1 + (int64_t)D.offa);
   const uint64_t x2 = (uint64_t)(h + (int64_t)D.offb);
-  const uint64_t s = x0 + shoup_approx(x1, D.w32, D.w32p, nq) +
-                     shoup_approx(x2, D.w64, D.w64p, nq);  // < 2^55 + 8q < 2^58
-  const uint64_t r = shoup_approx(s, 1, P.one, nq);       // [0, 4q)
-  return csub(csub(r, 2 * P.q), P.q);
+  return x0 + shoup_approx(x1, D.w32, D.w32p, D.nq) +
+         shoup_approx(x2, D.w64, D.w64p, D.nq);  // < 2^55 + 8q < 2^58
 }
 
 // One workgroup: 64 rows x 32 chunks of kMfmaSlots consecutive slots of one
 // limb.  Wave w owns rows 16w .. 16w + 15 of the tile and both 16-chunk
-// column tiles; its query fragments come straight from global memory, the
-// chunk tile's database digits are staged in LDS (global_load_lds, double
-// buffered across slots).  Workgroups are numbered so that the tiles of one
-// slot range run back to back on one XCD, which shares the operands in its L2.
+// column tiles; its query fragments come straight from global memory into
+// registers, the chunk tile's database digits are staged in LDS by DMA
+// (global_load_lds), double buffered across slots.  Every memory operation
+// of the slot loop is unconditional (sources clamped, the sums buffer padded
+// to whole tiles), so the loop body is straight-line code whose memory
+// counters the compiler tracks exactly.  Per slot: the fragments of the
+// second step are loaded before the first step's MFMAs; after the MFMAs the
+// DMA of the next slot's tile and the loads of its first-step fragments are
+// issued and land while this slot's sums are folded; a wait for all but the
+// 7 newest vector memory operations (those loads) retires this wave's DMA
+// before the barrier that publishes the tile, and the stores go out after
+// it.  A buffer is never the target of a DMA while it is read: it was read
+// in the previous slot, before that slot's barrier.  Workgroups are numbered
+// so that the tiles of one slot range run back to back on one XCD, which
+// shares the operands in its L2.
 template <int NKS>
 __global__ void __launch_bounds__(256, 2)
 k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R, int C, int L,
-           int logN, int n_items, PrimeSet ps, DigitSet ds, uint64_t* __restrict__ sums) {
+           int logN, int n_items, DigitSet ds, uint64_t* __restrict__ sums) {
   constexpr int Dp = 64 * NKS, Sk = 7 * Dp + 16;
   constexpr int BU = kMfmaChunks * Sk / 16;  // 16-byte units of one staged tile
-  constexpr int BR = (BU + 255) / 256;
-  __shared__ uint4 sb0[BU], sb1[BU];
+  constexpr int BR = (BU + 255) / 256;       // DMA rounds of the 256 threads
+  __shared__ uint4 sb0[BR * 256], sb1[BR * 256];
   const int N = 1 << logN;
   const int per_xcd = (n_items + 7) >> 3;
   const int lin = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (lin >= n_items) return;
   const int nrt = (R + kMfmaRows - 1) / kMfmaRows, nct = (C + kMfmaChunks - 1) / kMfmaChunks;
+  const int Rp = nrt * kMfmaRows, Cp = nct * kMfmaChunks;
   const int tile = lin % (nrt * nct), sg = lin / (nrt * nct);
   const int rt = tile % nrt, ctile = tile / nrt;
   const int l = sg % L, p0 = (sg / L) * kMfmaSlots;
   const int k0 = ctile * kMfmaChunks;
-  const int nk = C - k0 < kMfmaChunks ? C - k0 : kMfmaChunks;
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   const int m16 = lane & 15, g = lane >> 4;
   const int wrow0 = rt * kMfmaRows + 16 * w;
-  const bool idle = wrow0 >= R;  // uniform over the wave
   const int arow = wrow0 + m16 < R ? wrow0 + m16 : R - 1;
-  const Prime& P = ps.p[l];
   const DigitConst& D = ds.c[l];
-  const uint64_t nq = 0 - P.q;
-  const int bunits = nk * Sk / 16;
+  const int bunits = (C - k0 < kMfmaChunks ? C - k0 : kMfmaChunks) * Sk / 16;
 
   auto stage = [&](int p, uint4* buf) {
     const uint4* src =
@@ -181,70 +192,85 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
 #pragma unroll
     for (int m = 0; m < BR; ++m) {
       const int u = tid + 256 * m;
-      if (u < bunits)
-        __builtin_amdgcn_global_load_lds(
-            (const void*)(src + u),
-            (__attribute__((address_space(3))) void*)(buf + 256 * m + 64 * w), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(
+          (const void*)(src + (u < bunits ? u : 0)),
+          (__attribute__((address_space(3))) void*)(buf + 256 * m + 64 * w), 16, 0, 0);
     }
   };
+  // Query fragments of one 64-coordinate step of slot p.
+  auto load_a = [&](int p, int ks, v4i (&af)[7]) {
+    const int8_t* ab =
+        qd + (((size_t)l * N + p) * R + arow) * (size_t)(7 * Dp) + 16 * g + 64 * ks;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) af[a] = *reinterpret_cast<const v4i*>(ab + a * Dp);
+  };
+  // 98 MFMAs of one step: every digit pair (a, b) of both column tiles into
+  // diagonal a + b; the first product of a diagonal starts from a zero
+  // accumulator (b = 0, or a = 6 for the diagonals above 6).
+  auto mfma_step = [&](const v4i (&af)[7], int ks, const int8_t* bbase, v4i (&acc)[2][13]) {
+#pragma unroll
+    for (int b = 0; b < 7; ++b)
+#pragma unroll
+      for (int cs = 0; cs < 2; ++cs) {
+        const v4i bf = *reinterpret_cast<const v4i*>(bbase + cs * 16 * Sk + b * Dp + 64 * ks);
+#pragma unroll
+        for (int a = 0; a < 7; ++a)
+          acc[cs][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+              af[a], bf, (ks == 0 && (b == 0 || a == 6)) ? v4i{0, 0, 0, 0} : acc[cs][a + b], 0,
+              0, 0);
+      }
+  };
 
+  v4i a0[7], a1[7];
   stage(p0, sb0);
+  load_a(p0, 0, a0);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int jj = 0; jj < kMfmaSlots; ++jj) {
     const int p = p0 + jj;
+    // the last slot restages itself into the idle buffer (keeps the body uniform)
+    const int pn = jj + 1 < kMfmaSlots ? p + 1 : p;
     const uint4* cur = (jj & 1) ? sb1 : sb0;
-    if (jj + 1 < kMfmaSlots) stage(p + 1, (jj & 1) ? sb0 : sb1);
-    if (!idle) {
-      v4i acc[2][13];
-      const int8_t* abase = qd + (((size_t)l * N + p) * R + arow) * (size_t)(7 * Dp) + 16 * g;
-      const int8_t* bbase = reinterpret_cast<const int8_t*>(cur) + m16 * Sk + 16 * g;
+    if (NKS == 2) load_a(p, 1, a1);
+    __builtin_amdgcn_sched_barrier(0);  // issue those loads before the first step
+    v4i acc[2][13];
+    const int8_t* bbase = reinterpret_cast<const int8_t*>(cur) + m16 * Sk + 16 * g;
+    mfma_step(a0, 0, bbase, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    if (NKS == 2) mfma_step(a1, 1, bbase, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    stage(pn, (jj & 1) ? sb0 : sb1);
+    load_a(pn, 0, a0);
+    __builtin_amdgcn_sched_barrier(0);
+    // lane holds rows 4g .. 4g + 3 of the wave's 16, chunk m16 of each column tile
+    uint64_t v[2][4];
 #pragma unroll
-      for (int ks = 0; ks < NKS; ++ks) {
-        v4i af[7];
+    for (int cs = 0; cs < 2; ++cs)
 #pragma unroll
-        for (int a = 0; a < 7; ++a)
-          af[a] = *reinterpret_cast<const v4i*>(abase + a * Dp + 64 * ks);
+      for (int e = 0; e < 4; ++e) {
+        int32_t S[13];
 #pragma unroll
-        for (int b = 0; b < 7; ++b)
-#pragma unroll
-          for (int cs = 0; cs < 2; ++cs) {
-            const v4i bf =
-                *reinterpret_cast<const v4i*>(bbase + cs * 16 * Sk + b * Dp + 64 * ks);
-            // the first product of diagonal a + b starts from a zero
-            // accumulator (b = 0, or a = 6 for the diagonals above 6)
-#pragma unroll
-            for (int a = 0; a < 7; ++a)
-              acc[cs][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                  af[a], bf, (ks == 0 && (b == 0 || a == 6)) ? v4i{0, 0, 0, 0} : acc[cs][a + b],
-                  0, 0, 0);
-          }
+        for (int s = 0; s < 13; ++s) S[s] = acc[cs][s][e];
+        v[cs][e] = fold_digit_sums(S, D);
       }
-      // lane holds rows 4g .. 4g + 3 of the wave's 16, chunk m16 of each column tile
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(kWaitAllBut7Vmem);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_barrier();
+    uint64_t* dst = sums + (((size_t)l * N + p) * Rp + wrow0 + 4 * g) * Cp + k0 + m16;
 #pragma unroll
-      for (int cs = 0; cs < 2; ++cs) {
-        const int kk = cs * 16 + m16;
+    for (int cs = 0; cs < 2; ++cs)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          int32_t S[13];
-#pragma unroll
-          for (int s = 0; s < 13; ++s) S[s] = acc[cs][s][e];
-          const uint64_t v = fold_digit_sums(S, P, D, nq);
-          const int row = wrow0 + 4 * g + e;
-          if (row < R && kk < nk) sums[(((size_t)l * N + p) * R + row) * C + k0 + kk] = v;
-        }
-      }
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+      for (int e = 0; e < 4; ++e) dst[(size_t)e * Cp + 16 * cs] = v[cs][e];
   }
 }
 
-// Slot-major sums [L][N][R][C] -> ciphertexts [Q C][2][L][N] (output m = q C + k,
-// component c = row & 1): 64 slots x 32 chunks of one row per workgroup.
+// Slot-major sums [L][N][Rp][Cp] (values below 2^58) -> ciphertexts
+// [Q C][2][L][N] reduced to [0, q) (output m = q C + k, component c = row & 1):
+// 64 slots x 32 chunks of one row per workgroup.
 __global__ void __launch_bounds__(256)
 k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R, int C, int L,
-             int logN) {
+             int logN, PrimeSet ps) {
   __shared__ uint64_t t[32][65];
   const int N = 1 << logN;
   const int ng = N / 64, nkg = (C + 31) / 32;
@@ -256,16 +282,23 @@ k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R
   const int pg = b % ng, l = b / ng;
   const int p0 = pg * 64, k0 = kg * 32;
   const int tid = threadIdx.x;
+  const int Rp = (R + kMfmaRows - 1) / kMfmaRows * kMfmaRows;
+  const int Cp = (C + kMfmaChunks - 1) / kMfmaChunks * kMfmaChunks;
   for (int idx = tid; idx < 64 * 32; idx += 256) {
     const int kk = idx % 32, pp = idx / 32;
-    if (k0 + kk < C) t[kk][pp] = sums[(((size_t)l * N + p0 + pp) * R + row) * C + k0 + kk];
+    if (k0 + kk < C) t[kk][pp] = sums[(((size_t)l * N + p0 + pp) * Rp + row) * Cp + k0 + kk];
   }
   __syncthreads();
   const int q = row >> 1, c = row & 1;
+  const Prime& P = ps.p[l];
+  const uint64_t nq = 0 - P.q;
   for (int idx = tid; idx < 64 * 32; idx += 256) {
     const int pp = idx % 64, kk = idx / 64;
-    if (k0 + kk < C)
-      ct[((((size_t)q * C + k0 + kk) * 2 + c) * L + l) * N + p0 + pp] = t[kk][pp];
+    if (k0 + kk < C) {
+      const uint64_t r = shoup_approx(t[kk][pp], 1, P.one, nq);  // [0, 4q)
+      ct[((((size_t)q * C + k0 + kk) * 2 + c) * L + l) * N + p0 + pp] =
+          csub(csub(r, 2 * P.q), P.q);
+    }
   }
 }
 
@@ -274,6 +307,11 @@ k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R
 // --------------------------------------------------------------------------
 
 int mfma_padded_d(int d) { return (d + 63) / 64 * 64; }
+size_t mfma_sums_bytes(int Q, int C, int L, int logN) {
+  const size_t Rp = (2 * (size_t)Q + kMfmaRows - 1) / kMfmaRows * kMfmaRows;
+  const size_t Cp = ((size_t)C + kMfmaChunks - 1) / kMfmaChunks * kMfmaChunks;
+  return (size_t)L * ((size_t)1 << logN) * Rp * Cp * sizeof(uint64_t);
+}
 int mfma_db_stride(int d) { return 7 * mfma_padded_d(d) + 16; }
 
 bool mfma_supported(int logN, int d) {
@@ -304,14 +342,13 @@ hipError_t launch_db_digits(const uint2* dbres, int8_t* dbd, int C, int d, int L
 
 template <int NKS>
 static void launch_mac_mfma_t(const int8_t* qd, const int8_t* dbd, int R, int C, int L, int logN,
-                              const PrimeSet& ps, const DigitSet& ds, uint64_t* sums,
-                              hipStream_t st) {
+                              const DigitSet& ds, uint64_t* sums, hipStream_t st) {
   const int N = 1 << logN;
   const long n_items = (long)L * (N / kMfmaSlots) * ((R + kMfmaRows - 1) / kMfmaRows) *
                        ((C + kMfmaChunks - 1) / kMfmaChunks);
   const long per_xcd = (n_items + 7) >> 3;
   hipLaunchKernelGGL(k_mac_mfma<NKS>, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, st, qd, dbd,
-                     R, C, L, logN, (int)n_items, ps, ds, sums);
+                     R, C, L, logN, (int)n_items, ds, sums);
 }
 
 hipError_t launch_mac_mfma(const int8_t* qd, const int8_t* dbd, int Q, int d, int C, int L,
@@ -321,8 +358,8 @@ hipError_t launch_mac_mfma(const int8_t* qd, const int8_t* dbd, int Q, int d, in
   if (Q <= 0 || C <= 0) return hipSuccess;
   const int R = 2 * Q;
   switch (mfma_padded_d(d) / 64) {
-    case 1: launch_mac_mfma_t<1>(qd, dbd, R, C, L, logN, ps, ds, sums, st); break;
-    case 2: launch_mac_mfma_t<2>(qd, dbd, R, C, L, logN, ps, ds, sums, st); break;
+    case 1: launch_mac_mfma_t<1>(qd, dbd, R, C, L, logN, ds, sums, st); break;
+    case 2: launch_mac_mfma_t<2>(qd, dbd, R, C, L, logN, ds, sums, st); break;
     default: return hipErrorInvalidValue;
   }
   hipError_t e = hipGetLastError();
@@ -330,7 +367,7 @@ hipError_t launch_mac_mfma(const int8_t* qd, const int8_t* dbd, int Q, int d, in
   const int N = 1 << logN;
   const long nb = (long)L * (N / 64) * R * ((C + 31) / 32);
   hipLaunchKernelGGL(k_sums_to_ct, dim3((unsigned)nb), dim3(256), 0, st, sums, ct_out, R, C, L,
-                     logN);
+                     logN, ps);
   return hipGetLastError();
 }
 

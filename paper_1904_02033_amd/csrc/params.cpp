@@ -158,6 +158,7 @@ DigitConst digit_consts(uint64_t q) {
   D.w64p = shoup_companion(D.w64, q);
   D.offa = (((1ull << 53) + q - 1) / q) * q;
   D.offb = (((1ull << 57) + q - 1) / q) * q;
+  D.nq = 0 - q;
   return D;
 }
 

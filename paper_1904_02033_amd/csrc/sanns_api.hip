@@ -246,10 +246,10 @@ WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M) {
   off += align256(kPersistCtrlWords * sizeof(uint32_t));
   w.qdig = w.sums = off;
   if (ctx->digit_db && mfma_supported(ctx->logN, (int)d)) {
-    // matrix-core schedule: query digits and slot-major sums (2Q rows x C = 2M)
+    // matrix-core schedule: query digits and slot-major sums (all pairs: C = M / Q)
     off += align256(L * N * 2 * Q * 7 * (size_t)mfma_padded_d((int)d));
     w.sums = off;
-    off += align256(L * N * 2 * (size_t)M * 8);
+    off += align256(mfma_sums_bytes((int)Q, (int)((M + Q - 1) / Q), (int)L, ctx->logN));
   }
   w.total = off;
   return w;
