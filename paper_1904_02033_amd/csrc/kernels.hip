@@ -34,15 +34,22 @@ __device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, const Prime& 
 // forward / inverse transforms of independent polynomials
 // --------------------------------------------------------------------------
 
-// Forward transform of polynomial p (limb p % L) by one workgroup.  With
-// split set the output residues are stored as their 27-bit halves (uint2),
-// the form the multiply-accumulate kernels consume.
+// Forward transform of polynomial p (limb p % L) by one workgroup.  Output
+// forms (split):
+//   0  uint64 residues, polynomial-major like the input;
+//   1  27-bit halves (uint2), polynomial-major: the form the 64-bit
+//      multiply-accumulate kernels consume;
+//   2  uint64 residues grouped by 32 slots, [L][R][N/32][d][32] with rows
+//      r = 2q + c (R = 2Q) for polynomial p = ((q d + i) 2 + c) L + l: each
+//      32-slot group of a row is one contiguous block over the coordinates,
+//      the form the digit transpose of the matrix-core schedule reads.
 template <int LOGN>
 __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
                                              const uint64_t* __restrict__ in,
                                              uint64_t* __restrict__ out, int L,
                                              const PrimeSet& ps, const TwSet& tws,
-                                             uint32_t* err, int split) {
+                                             uint32_t* err, int split, int d = 0,
+                                             int R = 0) {
   constexpr int N = NttShape<LOGN>::N;
   const int l = p % L;
   const Prime& P = ps.p[l];
@@ -57,7 +64,15 @@ __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
   if (bad && err) atomicOr(err, 1u);
   ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P);
   uint64_t* dst = out + (size_t)p * N;
-  if (split) {
+  if (split == 2) {
+    const int c = (p / L) & 1, i = (p / (2 * L)) % d, q = p / (2 * L * d);
+    uint64_t* base = out + (((size_t)l * R + 2 * q + c) * (N / 32) * d + i) * 32;
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      const int s = ntt_slot<LOGN>(tid, a);
+      base[(size_t)(s >> 5) * d * 32 + (s & 31)] = v[a];
+    }
+  } else if (split) {
     uint2* dst2 = reinterpret_cast<uint2*>(dst);
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
@@ -75,9 +90,9 @@ __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
 template <int LOGN>
 __global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
 k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int L, PrimeSet ps,
-          TwSet tws, uint32_t* err, int split) {
+          TwSet tws, uint32_t* err, int split, int d, int R) {
   extern __shared__ uint64_t lds[];
-  ntt_fwd_poly<LOGN>(blockIdx.x, threadIdx.x, lds, in, out, L, ps, tws, err, split);
+  ntt_fwd_poly<LOGN>(blockIdx.x, threadIdx.x, lds, in, out, L, ps, tws, err, split, d, R);
 }
 
 // In-place inverse transform, result multiplied by N^-1 and in [0, q).
@@ -1258,12 +1273,14 @@ static void ntt_launch(K kern, unsigned grid, hipStream_t st, A... args) {
 
 hipError_t launch_ntt_fwd(const uint64_t* in, uint64_t* out, int n_polys, int logN, int L,
                           const PrimeSet& ps, const TwSet& tws, uint32_t* err, int split,
-                          hipStream_t st) {
+                          hipStream_t st, int d, int R) {
   if (n_polys <= 0) return hipSuccess;
+  if (split == 2 && (logN < 5 || d <= 0 || n_polys != R * d * L)) return hipErrorInvalidValue;
   switch (logN) {
-#define SANNS_CASE(LG)                                                                   \
-  case LG:                                                                               \
-    ntt_launch<LG>(k_ntt_fwd<LG>, (unsigned)n_polys, st, in, out, L, ps, tws, err, split); \
+#define SANNS_CASE(LG)                                                                 \
+  case LG:                                                                             \
+    ntt_launch<LG>(k_ntt_fwd<LG>, (unsigned)n_polys, st, in, out, L, ps, tws, err, split, \
+                   d, R);                                                              \
     break;
     SANNS_LOGN_CASES(SANNS_CASE)
 #undef SANNS_CASE

@@ -9,11 +9,12 @@ namespace sanns {
 #define SANNS_MAC_SHAPES(X) \
   X(1, 1) X(1, 2) X(1, 4) X(1, 8) X(2, 2) X(2, 4) X(4, 2) X(2, 3) X(3, 2)
 
-// split: store the NTT residues as 27-bit halves (uint2) for the
-// multiply-accumulate kernels.
+// split: output form of the NTT residues (0 plain, 1 27-bit halves for the
+// 64-bit multiply-accumulate kernels, 2 grouped by 32 slots for the digit
+// transpose, which needs d and R = 2Q with n_polys = R d L).
 hipError_t launch_ntt_fwd(const uint64_t* in, uint64_t* out, int n_polys, int logN, int L,
                           const PrimeSet& ps, const TwSet& tws, uint32_t* err, int split,
-                          hipStream_t st);
+                          hipStream_t st, int d = 0, int R = 0);
 hipError_t launch_ntt_inv(uint64_t* io, int n_polys, int logN, int L, const PrimeSet& ps,
                           const TwSet& tws, hipStream_t st);
 hipError_t launch_masks(const MaskKey& K, const uint64_t* qids, const uint32_t* work, int C,
@@ -83,7 +84,8 @@ constexpr int kMfmaMaxD = 128;     // largest d (two MFMA steps of 64 coordinate
 bool mfma_supported(int logN, int d);
 int mfma_padded_d(int d);   // d rounded up to 64
 int mfma_db_stride(int d);  // bytes per (limb, slot, chunk) of the database digits
-// Query NTT form [Q][d][2][L][N] uint64 -> query digits [L][N][2Q][7][Dp].
+// Query NTT form grouped by 32 slots ([L][2Q][N/32][d][32] uint64, NTT output
+// form 2) -> query digits [L][N][2Q][7][Dp].
 hipError_t launch_query_digits(const uint64_t* qntt, int8_t* qd, int Q, int d, int L, int logN,
                                hipStream_t st);
 // Database residues [L][C][d][N] (halves) -> database digits [L][N][C][Sk].

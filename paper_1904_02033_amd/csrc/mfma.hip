@@ -57,10 +57,11 @@ __device__ __forceinline__ uint32_t gather_byte(uint64_t y0, uint64_t y1, uint64
 
 // Transpose-and-digitise: a workgroup takes kDigitSlots consecutive slots of
 // one (limb, entity) pair, where the entity is a query row (source: the
-// query NTT form [Q][d][2][L][N] uint64) or a database chunk (source: the
-// database residues [L][C][d][N] as 27-bit halves), stages the d x 32 words in
-// LDS, and writes each slot's 7 digit rows of Dp bytes (16 bytes per store,
-// zero digits past coordinate d).
+// query NTT form grouped by 32 slots, [L][R][N/32][d][32] uint64, so the
+// workgroup's d x 32 words are one contiguous block) or a database chunk
+// (source: the database residues [L][C][d][N] as 27-bit halves), stages the
+// words in LDS, and writes each slot's 7 digit rows of Dp bytes (16 bytes per
+// store, zero digits past coordinate d).
 template <bool DB>
 __global__ void __launch_bounds__(256)
 k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, int d, int Dp,
@@ -84,9 +85,8 @@ k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, i
             src)[(((size_t)l * C + ent) * d + i) * N + p0 + pp];
         x = (uint64_t)h.x + ((uint64_t)h.y << 27);
       } else {
-        const int q = ent >> 1, c = ent & 1;
         x = reinterpret_cast<const uint64_t*>(
-            src)[((((size_t)q * d + i) * 2 + c) * L + l) * N + p0 + pp];
+            src)[(((size_t)l * n_ent + ent) * groups + pg) * d * kDigitSlots + idx];
       }
     }
     lw[i * P1 + pp] = digit_word(x);

@@ -560,7 +560,7 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
   };
   HIP_TRY(mark(SANNS_PHASE_QUERY_NTT, false));
   HIP_TRY(launch_ntt_fwd(ct_in, qntt, (int)(Q * d * 2 * L), ctx->logN, (int)L, ctx->ps,
-                         ctx->tws, ctx->d_err, mfma ? 0 : 1, st));
+                         ctx->tws, ctx->d_err, mfma ? 2 : 1, st, (int)d, (int)(2 * Q)));
   if (mfma)
     HIP_TRY(launch_query_digits(qntt, qdig, (int)Q, (int)d, (int)L, ctx->logN, st));
   HIP_TRY(mark(SANNS_PHASE_QUERY_NTT, true));
