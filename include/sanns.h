@@ -99,7 +99,8 @@ typedef struct sanns_ctx sanns_ctx;
  *            [L][N][n_chunks][7 Dp + 16] int8, Dp = d rounded up to 64: the
  *            same residues x as seven signed base-256 digits x_a in
  *            [-128, 127] (x = sum_a x_a 256^a), digit rows of Dp bytes
- *            indexed by coordinate, zero past d, then 16 padding bytes.
+ *            indexed by coordinate, zero past d, then 16 padding bytes;
+ *            followed by 64 KiB of slack the kernels may read.
  * Size: sanns_db_bytes(). */
 typedef struct {
     void *mem;

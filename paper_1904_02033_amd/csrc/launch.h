@@ -84,6 +84,7 @@ constexpr int kMfmaMaxD = 128;     // largest d (two MFMA steps of 64 coordinate
 bool mfma_supported(int logN, int d);
 int mfma_padded_d(int d);   // d rounded up to 64
 int mfma_db_stride(int d);  // bytes per (limb, slot, chunk) of the database digits
+size_t mfma_db_bytes(int C, int d, int L, int logN);  // the digit region, with its slack
 // Query NTT form grouped by 32 slots ([L][2Q][N/32][d][32] uint64, NTT output
 // form 2) -> query digits [L][N][2Q][7][Dp].
 hipError_t launch_query_digits(const uint64_t* qntt, int8_t* qd, int Q, int d, int L, int logN,

@@ -22,7 +22,7 @@
 //   database digits [L][N][C][Sk] int8       Sk = 7 Dp + 16: digit rows, then
 //                                            16 bytes of padding (LDS banks)
 //   slot-major sums [L][N][Rp][Cp] uint64 below 2^58, congruent mod q_l (R and
-//                   C padded to whole tiles of 64 rows and 32 chunks)
+//                   C padded to whole tiles of 64 rows and 64 chunks)
 // Fragment of one lane (row or column m = lane % 16, group g = lane / 16) at
 // step s: the 16 bytes of one digit row at coordinates 64s + 16g .. + 15.
 #include <hip/hip_runtime.h>
@@ -35,12 +35,19 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr uint64_t kDigitBias = 0x0080808080808080ull;  // 128 in each of bytes 0..6
 constexpr int kMfmaRows = 64;    // rows per workgroup: 4 waves x 16
-constexpr int kMfmaChunks = 32;  // chunks per workgroup: 2 MFMA column tiles
+constexpr int kMfmaChunks = 64;  // chunks per workgroup: 2 halves of 2 MFMA column tiles
 constexpr int kMfmaSlots = 8;    // consecutive slots per workgroup
 constexpr int kDigitSlots = 32;  // slots per workgroup of the digit transposes
-// s_waitcnt immediate (gfx9 encoding): vmcnt <= 7 (bits 3:0 and 15:14),
+// The database digit region ends with this many spare bytes: a staged half
+// tile may run past the last chunk (at most 32 chunks of at most 7 x 128 + 16
+// bytes each, plus one DMA round of 256 x 16 bytes).
+constexpr size_t kMfmaDbSlack = 64 * 1024;
+// s_waitcnt immediates (gfx9 encoding): vmcnt <= n (bits 3:0 and 15:14),
 // expcnt and lgkmcnt not waited for (7 in bits 6:4, 15 in bits 11:8).
-constexpr int kWaitAllBut7Vmem = 7 | (7 << 4) | (15 << 8);
+constexpr int vmcnt_wait(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+constexpr int kWaitAllVmem = vmcnt_wait(0);
+constexpr int kWaitAllBut7Vmem = vmcnt_wait(7);
+constexpr int kWaitAllBut14Vmem = vmcnt_wait(14);
 
 // The signed digits of x < 2^54 as the bytes of a word (byte 7 is zero).
 __device__ __forceinline__ uint64_t digit_word(uint64_t x) {
@@ -144,30 +151,33 @@ __device__ __forceinline__ uint64_t fold_digit_sums(const int32_t (&S)[13],
          shoup_approx(x2, D.w64, D.w64p, D.nq);  // < 2^55 + 8q < 2^58
 }
 
-// One workgroup: 64 rows x 32 chunks of kMfmaSlots consecutive slots of one
-// limb.  Wave w owns rows 16w .. 16w + 15 of the tile and both 16-chunk
-// column tiles; its query fragments come straight from global memory into
-// registers, the chunk tile's database digits are staged in LDS by DMA
-// (global_load_lds), double buffered across slots.  Every memory operation
-// of the slot loop is unconditional (sources clamped, the sums buffer padded
-// to whole tiles), so the loop body is straight-line code whose memory
-// counters the compiler tracks exactly.  Per slot: the fragments of the
-// second step are loaded before the first step's MFMAs; after the MFMAs the
-// DMA of the next slot's tile and the loads of its first-step fragments are
-// issued and land while this slot's sums are folded; a wait for all but the
-// 7 newest vector memory operations (those loads) retires this wave's DMA
-// before the barrier that publishes the tile, and the stores go out after
-// it.  A buffer is never the target of a DMA while it is read: it was read
-// in the previous slot, before that slot's barrier.  Workgroups are numbered
-// so that the tiles of one slot range run back to back on one XCD, which
-// shares the operands in its L2.
+// One workgroup: 64 rows x 64 chunks of kMfmaSlots consecutive slots of one
+// limb, the chunks taken as two halves of 32 that reuse the same query
+// fragments.  Wave w owns rows 16w .. 16w + 15 of the tile and the two
+// 16-chunk column tiles of the current half; its query fragments come
+// straight from global memory into registers, the half's database digits are
+// staged in LDS by DMA (global_load_lds): a slot's first half in sb0, its
+// second in sb1.  A DMA is issued once the MFMAs of the half before it have
+// read their buffer (an LDS read is not issued while a DMA into LDS is in
+// flight) and lands while that half's sums are folded.  Every memory
+// operation of the slot loop is unconditional (the digit region has slack
+// past its end, the sums buffer is padded to whole tiles), so the loop body is
+// straight-line code whose memory counters the compiler tracks exactly.
+// Query fragments are loaded one step ahead during the second half: those of
+// the next slot's first step while this slot's second step is multiplied,
+// those of its second step while the sums are folded.  Before each barrier
+// that publishes a buffer, a counted wait retires this wave's DMA into it
+// (and nothing newer); the stores go out after the barrier.  Workgroups are
+// numbered so that the tiles of one slot range run back to back on one XCD,
+// which shares the operands in its L2.
 template <int NKS>
 __global__ void __launch_bounds__(256, 2)
 k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R, int C, int L,
            int logN, int n_items, DigitSet ds, uint64_t* __restrict__ sums) {
   constexpr int Dp = 64 * NKS, Sk = 7 * Dp + 16;
-  constexpr int BU = kMfmaChunks * Sk / 16;  // 16-byte units of one staged tile
-  constexpr int BR = (BU + 255) / 256;       // DMA rounds of the 256 threads
+  constexpr int H = kMfmaChunks / 2;        // chunks per half
+  constexpr int BU = H * Sk / 16;           // 16-byte units of one staged half
+  constexpr int BR = (BU + 255) / 256;      // DMA rounds of the 256 threads
   __shared__ uint4 sb0[BR * 256], sb1[BR * 256];
   const int N = 1 << logN;
   const int per_xcd = (n_items + 7) >> 3;
@@ -184,18 +194,18 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
   const int wrow0 = rt * kMfmaRows + 16 * w;
   const int arow = wrow0 + m16 < R ? wrow0 + m16 : R - 1;
   const DigitConst& D = ds.c[l];
-  const int bunits = (C - k0 < kMfmaChunks ? C - k0 : kMfmaChunks) * Sk / 16;
-
-  auto stage = [&](int p, uint4* buf) {
-    const uint4* src =
-        reinterpret_cast<const uint4*>(dbd + (((size_t)l * N + p) * C + k0) * Sk);
+  // DMA of half h of slot p's database tile into buf.  Units past the last
+  // chunk read the following bytes of the digit region (the next slot's
+  // chunks, or the region's slack of kMfmaDbSlack bytes at its end): data in
+  // rows whose sums nobody reads.
+  auto stage = [&](int p, int h, uint4* buf) {
+    const uint4* src = reinterpret_cast<const uint4*>(
+        dbd + (((size_t)l * N + p) * C + k0 + h * H) * Sk);
 #pragma unroll
-    for (int m = 0; m < BR; ++m) {
-      const int u = tid + 256 * m;
+    for (int m = 0; m < BR; ++m)
       __builtin_amdgcn_global_load_lds(
-          (const void*)(src + (u < bunits ? u : 0)),
+          (const void*)(src + tid + 256 * m),
           (__attribute__((address_space(3))) void*)(buf + 256 * m + 64 * w), 16, 0, 0);
-    }
   };
   // Query fragments of one 64-coordinate step of slot p.
   auto load_a = [&](int p, int ks, v4i (&af)[7]) {
@@ -220,30 +230,8 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
               0, 0);
       }
   };
-
-  v4i a0[7], a1[7];
-  stage(p0, sb0);
-  load_a(p0, 0, a0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  for (int jj = 0; jj < kMfmaSlots; ++jj) {
-    const int p = p0 + jj;
-    // the last slot restages itself into the idle buffer (keeps the body uniform)
-    const int pn = jj + 1 < kMfmaSlots ? p + 1 : p;
-    const uint4* cur = (jj & 1) ? sb1 : sb0;
-    if (NKS == 2) load_a(p, 1, a1);
-    __builtin_amdgcn_sched_barrier(0);  // issue those loads before the first step
-    v4i acc[2][13];
-    const int8_t* bbase = reinterpret_cast<const int8_t*>(cur) + m16 * Sk + 16 * g;
-    mfma_step(a0, 0, bbase, acc);
-    __builtin_amdgcn_sched_barrier(0);
-    if (NKS == 2) mfma_step(a1, 1, bbase, acc);
-    __builtin_amdgcn_sched_barrier(0);
-    stage(pn, (jj & 1) ? sb0 : sb1);
-    load_a(pn, 0, a0);
-    __builtin_amdgcn_sched_barrier(0);
-    // lane holds rows 4g .. 4g + 3 of the wave's 16, chunk m16 of each column tile
-    uint64_t v[2][4];
+  // Fold of the accumulators of one half into sums below 2^58.
+  auto fold = [&](const v4i (&acc)[2][13], uint64_t (&v)[2][4]) {
 #pragma unroll
     for (int cs = 0; cs < 2; ++cs)
 #pragma unroll
@@ -253,15 +241,67 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
         for (int s = 0; s < 13; ++s) S[s] = acc[cs][s][e];
         v[cs][e] = fold_digit_sums(S, D);
       }
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(kWaitAllBut7Vmem);
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_barrier();
-    uint64_t* dst = sums + (((size_t)l * N + p) * Rp + wrow0 + 4 * g) * Cp + k0 + m16;
+  };
+  // lane holds rows 4g .. 4g + 3 of the wave's 16, chunk m16 of each column tile
+  auto store = [&](int p, int h, const uint64_t (&v)[2][4]) {
+    uint64_t* dst =
+        sums + (((size_t)l * N + p) * Rp + wrow0 + 4 * g) * Cp + k0 + h * H + m16;
 #pragma unroll
     for (int cs = 0; cs < 2; ++cs)
 #pragma unroll
       for (int e = 0; e < 4; ++e) dst[(size_t)e * Cp + 16 * cs] = v[cs][e];
+  };
+
+  const int8_t* b0 = reinterpret_cast<const int8_t*>(sb0) + m16 * Sk + 16 * g;
+  const int8_t* b1 = reinterpret_cast<const int8_t*>(sb1) + m16 * Sk + 16 * g;
+  v4i a0[7], a1[7];
+  stage(p0, 0, sb0);
+  load_a(p0, 0, a0);
+  if (NKS == 2) load_a(p0, 1, a1);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  for (int jj = 0; jj < kMfmaSlots; ++jj) {
+    const int p = p0 + jj;
+    // the last slot restages itself (keeps the body uniform)
+    const int pn = jj + 1 < kMfmaSlots ? p + 1 : p;
+    uint64_t v[2][4];
+    {  // first half: chunks k0 .. k0 + 31 from sb0; then the second half's DMA
+      v4i acc[2][13];
+      mfma_step(a0, 0, b0, acc);
+      if (NKS == 2) mfma_step(a1, 1, b0, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      stage(p, 1, sb1);
+      __builtin_amdgcn_sched_barrier(0);
+      fold(acc, v);
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_waitcnt(kWaitAllVmem);  // the DMA into sb1
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_barrier();
+      store(p, 0, v);
+    }
+    {  // second half from sb1; then the next slot's first half and fragments
+      v4i acc[2][13];
+      mfma_step(a0, 0, b1, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      if (NKS == 2) {
+        load_a(pn, 0, a0);  // step 0 of the next slot, during this step 1
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_step(a1, 1, b1, acc);
+        __builtin_amdgcn_sched_barrier(0);
+        stage(pn, 0, sb0);
+        load_a(pn, 1, a1);  // step 1 of the next slot, during the fold
+      } else {
+        stage(pn, 0, sb0);
+        load_a(pn, 0, a0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      fold(acc, v);
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_waitcnt(kWaitAllBut7Vmem);  // the DMA into sb0
+      __builtin_amdgcn_sched_barrier(0);
+      __builtin_amdgcn_s_barrier();
+      store(p, 1, v);
+    }
   }
 }
 
@@ -313,6 +353,9 @@ size_t mfma_sums_bytes(int Q, int C, int L, int logN) {
   return (size_t)L * ((size_t)1 << logN) * Rp * Cp * sizeof(uint64_t);
 }
 int mfma_db_stride(int d) { return 7 * mfma_padded_d(d) + 16; }
+size_t mfma_db_bytes(int C, int d, int L, int logN) {
+  return (size_t)L * ((size_t)1 << logN) * C * mfma_db_stride(d) + kMfmaDbSlack;
+}
 
 bool mfma_supported(int logN, int d) {
   return logN >= 6 && d >= 1 && d <= kMfmaMaxD;

@@ -440,7 +440,7 @@ extern "C" size_t sanns_db_bytes(const sanns_ctx* ctx, uint32_t n_chunks, uint32
   if (!ctx) return 0;
   const size_t N = ctx->p.N, L = ctx->p.L;
   size_t b = L * n_chunks * d * N * 8 + (size_t)n_chunks * N * 4;
-  if (db_has_digits(ctx, d)) b += L * N * n_chunks * (size_t)mfma_db_stride((int)d);
+  if (db_has_digits(ctx, d)) b += mfma_db_bytes((int)n_chunks, (int)d, (int)L, ctx->logN);
   return b;
 }
 

@@ -154,7 +154,7 @@ def test_mfma_default_and_limits(stage):
     # the flag adds the digit form to the database size
     ctxd = _ctx(stage, pb, digits=True)
     plain = nat.sanns_db_bytes(ctx.handle, 3, 100)
-    assert nat.sanns_db_bytes(ctxd.handle, 3, 100) == plain + 2 * 4096 * 3 * (7 * 128 + 16)
+    assert nat.sanns_db_bytes(ctxd.handle, 3, 100) == plain + 2 * 4096 * 3 * (7 * 128 + 16) + 65536
     assert nat.sanns_db_bytes(ctxd.handle, 3, 200) == nat.sanns_db_bytes(ctx.handle, 3, 200)
     # d > 128: no digit form; forcing the schedule is a host error, the
     # default falls back to the vector schedule
