@@ -6,7 +6,8 @@ stand-in for SIFT), BFV with N = 8192, three 54-bit primes, t = 16957441.
 One step = one pass of the whole server hot path for a batch of 64 encrypted
 queries: query NTTs, multiply-accumulate over every chunk of the resident
 database, INTT, norm and mask, server shares out.  The step runs in the
-schedule the autotuner picks (a hipGraph of the per-phase kernels or one
+schedule the autotuner picks (a hipGraph of the per-phase kernels, with the
+64-bit vector or the int8-digit matrix-core multiply-accumulate, or one
 persistent work-queue launch, with their tile shapes), timed before the
 measured region.  Inputs are resident in HBM before the timed region.
 
@@ -37,13 +38,14 @@ METRIC = "encrypted distances/s at 1M×128 (batched vs plain); p50/p99 query lat
 UNIT = "encrypted distances/s"
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz 32-bit VALU lane-ops
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+MFMA_I8_PEAK_TOPS = 5000.0  # dense int8 MFMA, MI355X
 HBM_PEAK_GBS = 8000.0
 
 
 def device_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ["kernels.hip", "kernels.h", "modarith.h", "ntt.h"]:
+    for f in ["kernels.hip", "mfma.hip", "kernels.h", "modarith.h", "ntt.h"]:
         with open(os.path.join(ROOT, "paper_1904_02033_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -127,7 +129,9 @@ def run_linear(args, w):
     pts = synthdata.gen_points(w, n=args.n if w.cid != 1 else w.n)
     queries = synthdata.gen_queries(w, Q)
     n, d = pts.shape
-    ctx = stage.Context(w.N, w.L, w.t_bits)
+    params = nat.sanns_params_derive(w.N, w.L, w.t_bits)
+    params.flags |= nat.SANNS_FLAG_DIGIT_DB  # also keep the int8 digit form (matrix cores)
+    ctx = stage.Context(params=params)
     N, L, t = ctx.N, ctx.L, ctx.t
     slot = stage.linear_slot_map(n, N, synthdata.gen_perm(n, synthdata.SEED_PERM + w.cid))
     db = stage.encode_db(ctx, pts, slot)
@@ -204,23 +208,38 @@ def run_linear(args, w):
     best.apply(ctx)
     mulacc = Q * C * 2 * d * L * N
     mac_ms = phases["mac"]
-    mac_ops = 3 * mulacc  # 32x32->64 multiply-adds: Karatsuba on 27-bit halves
     variant = pbest.variant or 22  # the library's default all-pairs schedule
-    mac_kernel = "k_mac_dl" if variant >= 21 else "k_mac_lds"
-    if Q < 2:
-        mac_kernel = "k_mac"
-    if best.mode == nat.SANNS_MODE_PERSISTENT:
-        mac_ms, mac_kernel = pct(step_ms, 50), "k_persistent (whole step)"
-    mac_tops = mac_ops / (mac_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": mac_kernel,
-                "achieved": round(mac_tops, 3),
-                "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s (32-bit VALU lane-ops)",
-                "frac": round(mac_tops / VALU_PEAK_TOPS, 4),
-                "traffic": (recorded_traffic(mac_kernel.split()[0])
-                            if (w.cid == 2 and Q == 64) else None),
-                "traffic_unit": "bytes/launch",
-                "avg_ms": round(mac_ms, 4),
-                "algorithmic": f"{mac_ops:.4g} ops = 3 x {mulacc:.4g} modular mul-acc"}
+    traffic = None
+    if variant == autotune.MFMA_SCHEDULE and Q >= 2:
+        # int8 matrix cores: 49 digit-pair products per modular multiply-add
+        mac_kernel = "k_mac_mfma"
+        mac_ops = 2 * 49 * mulacc
+        mac_tops = mac_ops / (mac_ms * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "kernel": mac_kernel,
+                    "achieved": round(mac_tops, 3), "peak": MFMA_I8_PEAK_TOPS,
+                    "unit": "TOPS (int8 MFMA, dense)",
+                    "frac": round(mac_tops / MFMA_I8_PEAK_TOPS, 4),
+                    "algorithmic": f"{mac_ops:.4g} int8 ops = 2 x 49 x {mulacc:.4g} "
+                                   "digit-pair multiply-adds"}
+    else:
+        mac_ops = 3 * mulacc  # 32x32->64 multiply-adds: Karatsuba on 27-bit halves
+        mac_kernel = "k_mac_dl" if variant >= 21 else "k_mac_lds"
+        if Q < 2:
+            mac_kernel = "k_mac"
+        if best.mode == nat.SANNS_MODE_PERSISTENT:
+            mac_ms, mac_kernel = pct(step_ms, 50), "k_persistent (whole step)"
+        mac_tops = mac_ops / (mac_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "kernel": mac_kernel,
+                    "achieved": round(mac_tops, 3),
+                    "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s (32-bit VALU lane-ops)",
+                    "frac": round(mac_tops / VALU_PEAK_TOPS, 4),
+                    "algorithmic": f"{mac_ops:.4g} ops = 3 x {mulacc:.4g} modular mul-acc"}
+    if w.cid == 2 and Q == 64:
+        traffic = recorded_traffic(mac_kernel.split()[0])
+    roofline.update({"traffic": traffic, "traffic_unit": "bytes/launch",
+                     "avg_ms": round(mac_ms, 4)})
+    if traffic:
+        roofline["hbm_gbs"] = round(traffic / (mac_ms * 1e-3) / 1e9, 1)
     log(f"phases (ms): {phases}")
 
     if args.calib_copy_mib:
@@ -272,7 +291,8 @@ def run_linear(args, w):
         f"encrypted distances/s at {n:,}x{d} {kind}, {Q} queries per step",
         "value": round(value, 1), "unit": UNIT, "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64" if not best.label().endswith("mfma") else "u64 (int8 digit MFMA)",
         "data": "synthetic",
         "config": {"workload": f"batched linear scan: {n:,} x {d} {kind} ({w.gen}) "
                                f"database, {Q} encrypted queries per step, BFV N={N}, "

@@ -281,10 +281,13 @@ sanns_status sanns_device_status(sanns_ctx *ctx, void *stream);
 sanns_status sanns_set_schedule(sanns_ctx *ctx, int lds_variant, int qt, int ct);
 
 /* Phases timed by the profiler, in launch order. */
-#define SANNS_PHASE_QUERY_NTT 0 /* forward NTT of the query ciphertexts     */
+#define SANNS_PHASE_QUERY_NTT 0 /* forward NTT of the query ciphertexts
+                                   (and, SANNS_SCHEDULE_MFMA, their digits) */
 #define SANNS_PHASE_MASKS 1     /* ChaCha20 masks -> server shares          */
 #define SANNS_PHASE_MAC 2       /* multiply-accumulate over the database    */
-#define SANNS_PHASE_INTT_MASK 3 /* INTT + Delta [||p||^2 - r]_t             */
+#define SANNS_PHASE_INTT_MASK 3 /* INTT + Delta [||p||^2 - r]_t (and,
+                                   SANNS_SCHEDULE_MFMA, the transpose of the
+                                   slot-major sums before it)               */
 #define SANNS_N_PHASES 4
 
 /* Per-phase timing of the fused form (tracing aid).  While enabled,

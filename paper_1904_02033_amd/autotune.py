@@ -4,8 +4,9 @@ For one call shape (ring, limbs, d, queries, chunks, all-pairs or work list)
 it times every built schedule on the device with the caller's inputs:
 
   * SANNS_MODE_BATCHED (a hipGraph of the per-phase kernels) with each
-    LDS-staged multiply-accumulate variant (all-pairs) or each register tile
-    (work lists),
+    LDS-staged multiply-accumulate variant and, for contexts created with
+    SANNS_FLAG_DIGIT_DB, the int8 matrix-core schedule (all-pairs), or each
+    register tile (work lists),
   * SANNS_MODE_PERSISTENT (one work-queue launch) with each tile shape built
     for the ring degree,
 
@@ -27,6 +28,8 @@ from . import native as nat
 # Multiply-accumulate schedules built into the library (ids as in sanns.h).
 LDS_VARIANTS = list(range(1, 12)) + list(range(21, 28))   # all need N % 32 == 0
 REGISTER_TILES = [(1, 1), (1, 2), (1, 4), (1, 8), (2, 2), (2, 4), (4, 2), (2, 3), (3, 2)]
+MFMA_SCHEDULE = nat.SANNS_SCHEDULE_MFMA  # needs SANNS_FLAG_DIGIT_DB, d <= 128
+MFMA_MAX_D = 128
 # persistent tile shapes per log2 N, with the largest d each accumulates in one pass
 PERSIST_SHAPES = {11: [(61, 252)], 12: [(51, 252), (52, 252)],
                   13: [(41, 252), (42, 252), (43, 252), (44, 252)], 14: [(71, 254)]}
@@ -43,6 +46,8 @@ class Schedule:
     def label(self) -> str:
         if self.mode == nat.SANNS_MODE_PERSISTENT:
             return f"persistent/{self.variant}"
+        if self.variant == MFMA_SCHEDULE:
+            return "batched/mfma"
         if self.variant:
             return f"batched/lds{self.variant}"
         return f"batched/tile{self.qt}x{self.ct}"
@@ -56,6 +61,8 @@ def candidates(ctx, d: int, regular: bool, Q: int) -> List[Schedule]:
     out: List[Schedule] = []
     if regular and Q >= 2 and ctx.N % 32 == 0:
         out += [Schedule(nat.SANNS_MODE_BATCHED, v) for v in LDS_VARIANTS]
+        if (ctx.params.flags & nat.SANNS_FLAG_DIGIT_DB) and d <= MFMA_MAX_D and ctx.N >= 64:
+            out.append(Schedule(nat.SANNS_MODE_BATCHED, MFMA_SCHEDULE))
     else:
         out += [Schedule(nat.SANNS_MODE_BATCHED, 0, qt, ct) for qt, ct in REGISTER_TILES]
     out += [Schedule(nat.SANNS_MODE_PERSISTENT, s) for s, max_d in PERSIST_SHAPES.get(logN, [])

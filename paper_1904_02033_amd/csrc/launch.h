@@ -92,13 +92,14 @@ hipError_t launch_query_digits(const uint64_t* qntt, int8_t* qd, int Q, int d, i
 // Database residues [L][C][d][N] (halves) -> database digits [L][N][C][Sk].
 hipError_t launch_db_digits(const uint2* dbres, int8_t* dbd, int C, int d, int L, int logN,
                             hipStream_t st);
-// All-pairs sums into the slot-major buffer `sums` ([L][N][Rp][Cp] uint64,
-// Rp = 2Q and Cp = C rounded up to 64 and 32; mfma_sums_bytes), then reduced
-// and transposed into ct_out [Q C][2][L][N] (NTT form, residues in [0, q)).
+// All-pairs sums into the slot-major buffer `sums` ([L][N][Rp][Cp] uint64
+// below 2^58, Rp = 2Q and Cp = C rounded up to 64; mfma_sums_bytes).
 size_t mfma_sums_bytes(int Q, int C, int L, int logN);
 hipError_t launch_mac_mfma(const int8_t* qd, const int8_t* dbd, int Q, int d, int C, int L,
-                           int logN, const PrimeSet& ps, const DigitSet& ds, uint64_t* sums,
-                           uint64_t* ct_out, hipStream_t st);
+                           int logN, const DigitSet& ds, uint64_t* sums, hipStream_t st);
+// The sums reduced to [0, q) and transposed into ct_out [Q C][2][L][N] (NTT form).
+hipError_t launch_sums_to_ct(const uint64_t* sums, uint64_t* ct_out, int Q, int C, int L,
+                             int logN, const PrimeSet& ps, hipStream_t st);
 
 hipError_t launch_gather(const void* pts, int is_signed, long n, int d,
                          const int64_t* slot_point, long base, long total, int logN,

@@ -395,8 +395,7 @@ static void launch_mac_mfma_t(const int8_t* qd, const int8_t* dbd, int R, int C,
 }
 
 hipError_t launch_mac_mfma(const int8_t* qd, const int8_t* dbd, int Q, int d, int C, int L,
-                           int logN, const PrimeSet& ps, const DigitSet& ds, uint64_t* sums,
-                           uint64_t* ct_out, hipStream_t st) {
+                           int logN, const DigitSet& ds, uint64_t* sums, hipStream_t st) {
   if (!mfma_supported(logN, d)) return hipErrorInvalidValue;
   if (Q <= 0 || C <= 0) return hipSuccess;
   const int R = 2 * Q;
@@ -405,9 +404,14 @@ hipError_t launch_mac_mfma(const int8_t* qd, const int8_t* dbd, int Q, int d, in
     case 2: launch_mac_mfma_t<2>(qd, dbd, R, C, L, logN, ds, sums, st); break;
     default: return hipErrorInvalidValue;
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const int N = 1 << logN;
+  return hipGetLastError();
+}
+
+hipError_t launch_sums_to_ct(const uint64_t* sums, uint64_t* ct_out, int Q, int C, int L,
+                             int logN, const PrimeSet& ps, hipStream_t st) {
+  if (logN < 6) return hipErrorInvalidValue;
+  if (Q <= 0 || C <= 0) return hipSuccess;
+  const int R = 2 * Q, N = 1 << logN;
   const long nb = (long)L * (N / 64) * R * ((C + 31) / 32);
   hipLaunchKernelGGL(k_sums_to_ct, dim3((unsigned)nb), dim3(256), 0, st, sums, ct_out, R, C, L,
                      logN, ps);

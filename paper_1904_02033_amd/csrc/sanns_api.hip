@@ -571,8 +571,8 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
   HIP_TRY(mark(SANNS_PHASE_MAC, false));
   if (mfma) {
     const int8_t* dig = (const int8_t*)db->mem + (size_t)L * C * d * N * 8 + (size_t)C * N * 4;
-    HIP_TRY(launch_mac_mfma(qdig, dig, (int)Q, (int)d, (int)C, (int)L, ctx->logN, ctx->ps,
-                            ctx->ds, sums, ct_out, st));
+    HIP_TRY(launch_mac_mfma(qdig, dig, (int)Q, (int)d, (int)C, (int)L, ctx->logN, ctx->ds,
+                            sums, st));
   } else if (lds > 0)
     HIP_TRY(launch_mac_lds(lds, (const uint2*)qntt, res, (int)Q, (int)d, (int)L, ctx->logN,
                            (int)C, ctx->ps, ct_out, st));
@@ -581,6 +581,8 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
                        ctx->logN, (int)C, ctx->ps, ct_out, st));
   HIP_TRY(mark(SANNS_PHASE_MAC, true));
   HIP_TRY(mark(SANNS_PHASE_INTT_MASK, false));
+  if (mfma)
+    HIP_TRY(launch_sums_to_ct(sums, ct_out, (int)Q, (int)C, (int)L, ctx->logN, ctx->ps, st));
   HIP_TRY(launch_intt_mask(ct_out, share, norms, dwork, (int)C, (int)M, ctx->logN, (int)L,
                            (uint32_t)ctx->p.t, ctx->ps, ctx->tws, st));
   HIP_TRY(mark(SANNS_PHASE_INTT_MASK, true));
