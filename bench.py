@@ -68,6 +68,19 @@ def recorded_traffic(kernel: str):
     return None
 
 
+def parse_schedule(text, nat, autotune):
+    """'' (library default), 'mfma', 'lds<id>' or 'persistent/<id>'."""
+    if not text:
+        return autotune.Schedule(nat.SANNS_MODE_BATCHED)
+    if text == "mfma":
+        return autotune.Schedule(nat.SANNS_MODE_BATCHED, autotune.MFMA_SCHEDULE)
+    if text.startswith("lds"):
+        return autotune.Schedule(nat.SANNS_MODE_BATCHED, int(text[3:]))
+    if text.startswith("persistent/"):
+        return autotune.Schedule(nat.SANNS_MODE_PERSISTENT, int(text.split("/")[1]))
+    raise SystemExit(f"unknown schedule {text!r}")
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -96,6 +109,9 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner and run the library's default batched schedule "
                          "(used for profiler runs)")
+    ap.add_argument("--schedule", default="",
+                    help="with --no-tune: run this schedule instead of the default "
+                         "(mfma, lds<id>, persistent/<id>)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -151,7 +167,8 @@ def run_linear(args, w):
     from paper_1904_02033_amd import autotune
     tt = time.time()
     if args.no_tune:
-        best = autotune.Schedule(nat.SANNS_MODE_BATCHED)
+        best = parse_schedule(args.schedule, nat, autotune)
+        best.apply(ctx)
         best.ms = float("nan")
         timed = [best]
     else:
@@ -208,7 +225,9 @@ def run_linear(args, w):
     best.apply(ctx)
     mulacc = Q * C * 2 * d * L * N
     mac_ms = phases["mac"]
-    variant = pbest.variant or 22  # the library's default all-pairs schedule
+    # the library's default all-pairs schedule: matrix cores on a digit database
+    default = autotune.MFMA_SCHEDULE if (d <= autotune.MFMA_MAX_D and Q >= 2) else 22
+    variant = pbest.variant or default
     traffic = None
     if variant == autotune.MFMA_SCHEDULE and Q >= 2:
         # int8 matrix cores: 49 digit-pair products per modular multiply-add
