@@ -68,6 +68,20 @@ def recorded_traffic(kernel: str):
     return None
 
 
+USE_DIGITS = True
+
+
+def digit_context(w):
+    """Context of workload w whose databases also keep the int8 digit form
+    that the matrix-core multiply-accumulate reads (SANNS_FLAG_DIGIT_DB),
+    unless --no-digits."""
+    from paper_1904_02033_amd import native as nat, stage
+    params = nat.sanns_params_derive(w.N, w.L, w.t_bits)
+    if USE_DIGITS:
+        params.flags |= nat.SANNS_FLAG_DIGIT_DB
+    return stage.Context(params=params)
+
+
 def parse_schedule(text, nat, autotune):
     """'' (library default), 'mfma', 'lds<id>' or 'persistent/<id>'."""
     if not text:
@@ -106,13 +120,19 @@ def main():
                     choices=["batched-1Mx128", "batched-1Mx96", "linear-10Kx128",
                              "clustered-10M", "serving"])
     ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-rate", type=float, default=0.0,
+                    help="also serve one Poisson trace at this absolute rate (req/s)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner and run the library's default batched schedule "
                          "(used for profiler runs)")
+    ap.add_argument("--no-digits", action="store_true",
+                    help="create contexts without SANNS_FLAG_DIGIT_DB (vector schedules only)")
     ap.add_argument("--schedule", default="",
                     help="with --no-tune: run this schedule instead of the default "
                          "(mfma, lds<id>, persistent/<id>)")
     args = ap.parse_args()
+    global USE_DIGITS
+    USE_DIGITS = not args.no_digits
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the stage shards by database chunk; see the design notes)", flush=True)
@@ -145,9 +165,7 @@ def run_linear(args, w):
     pts = synthdata.gen_points(w, n=args.n if w.cid != 1 else w.n)
     queries = synthdata.gen_queries(w, Q)
     n, d = pts.shape
-    params = nat.sanns_params_derive(w.N, w.L, w.t_bits)
-    params.flags |= nat.SANNS_FLAG_DIGIT_DB  # also keep the int8 digit form (matrix cores)
-    ctx = stage.Context(params=params)
+    ctx = digit_context(w)
     N, L, t = ctx.N, ctx.L, ctx.t
     slot = stage.linear_slot_map(n, N, synthdata.gen_perm(n, synthdata.SEED_PERM + w.cid))
     db = stage.encode_db(ctx, pts, slot)
@@ -359,7 +377,7 @@ def clustered_world(dev, n_clusters=16384, total=9_900_000, stash=100_000):
     t0 = time.time()
     cdb = synthdata.gen_clustered(n_clusters=n_clusters, total_clustered=total, stash=stash,
                                   d=w.d, seed=synthdata.SEED_DATA + 4)
-    ctx = stage.Context(w.N, w.L, w.t_bits)
+    ctx = digit_context(w)
     srv = clustered.ClusteredServer(
         ctx, cdb.points, cdb.cluster_sizes, cdb.centers, cdb.stash_size,
         synthdata.gen_perm(n_clusters, synthdata.SEED_PERM + 4),
@@ -491,7 +509,7 @@ def run_serving(args):
     from paper_1904_02033_amd import native as nat, serve, stage
     dev = torch.device("cuda", 0)
     wA, wB = synthdata.WORKLOADS[2], synthdata.WORKLOADS[3]
-    ctxA = stage.Context(wA.N, wA.L, wA.t_bits)
+    ctxA = digit_context(wA)
     ptsA = synthdata.gen_points(wA, n=100_000, seed=synthdata.SEED_DATA + 5)
     dbA = stage.encode_db(ctxA, ptsA, stage.linear_slot_map(
         len(ptsA), ctxA.N, synthdata.gen_perm(len(ptsA), synthdata.SEED_PERM + 5)))
@@ -534,6 +552,11 @@ def run_serving(args):
         return req.Q * n_of[req.db]
 
     def serve_trace(reqs, max_batch, inflight, realtime):
+        # buffers cached by the previous trace's server go back to the device
+        # first (outside the timed region), so that one trace's pools cannot
+        # push the caching allocator into a synchronising retry in the next
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
         s = serve.Server(dbs, hbm_budget=64 << 30, max_inflight=inflight,
                          max_batch_queries=max_batch, client_select=select,
                          keep_outputs=False)
@@ -566,6 +589,11 @@ def run_serving(args):
                          True)
         log(f"rho={rho}: {st}")
         out[f"rho_{rho}"] = st
+    if args.serving_rate > 0:
+        st = serve_trace(make_requests(args.serving_rate, nreq, synthdata.SEED_ARR + 5), 64, 3,
+                         True)
+        log(f"rate {args.serving_rate} req/s: {st}")
+        out[f"rate_{args.serving_rate}"] = st
     # the per-query path: one query per launch, one launch at a time
     per_q = serve_trace(make_requests(1000.0, max(10, nreq // 10), synthdata.SEED_ARR + 5,
                                       per_query=True), 1, 1, False)

@@ -58,9 +58,10 @@ typedef enum {
 #define SANNS_FLAG_DIGIT_DB 2u      /* databases of dimension d <= 128 (and
                                        N >= 64) also hold their int8 digit
                                        form, which the matrix-core schedule
-                                       SANNS_SCHEDULE_MFMA reads; it becomes
-                                       the default schedule of all-pairs
-                                       batches of two or more queries      */
+                                       SANNS_SCHEDULE_MFMA reads; by default
+                                       all-pairs batches use it when a cost
+                                       model of the two schedules predicts
+                                       it faster (many queries and chunks) */
 
 /* BFV parameters (Section 2.3; Section 5 "Parameters").
  *   N    ring degree, power of two, 16 <= N <= 16384
@@ -210,7 +211,10 @@ sanns_status sanns_decrypt_shares(sanns_ctx *ctx, const int8_t *sk,
  * order (M = Q * n_chunks, m = q * n_chunks + k). */
 
 /* Bytes of device workspace sanns_distances needs for Q queries and M
- * outputs in the given mode. */
+ * outputs in the given mode, under the context's current schedule (a call
+ * that will run the matrix-core schedule, SANNS_SCHEDULE_MFMA, needs more;
+ * query the size again after sanns_set_schedule).  M = Q * n_chunks is
+ * sized for an all-pairs call. */
 size_t sanns_distances_workspace(const sanns_ctx *ctx, const sanns_db *db,
                                  uint32_t Q, uint32_t M, int mode);
 

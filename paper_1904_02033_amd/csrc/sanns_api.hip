@@ -136,14 +136,38 @@ bool db_has_digits(const sanns_ctx* ctx, uint32_t d) {
   return ctx->digit_db && mfma_supported(ctx->logN, (int)d);
 }
 
-void choose_shape(const sanns_ctx* ctx, uint32_t Q, uint32_t d, bool regular, double q_per_chunk,
-                  int& qt, int& ct, int& lds) {
+// Whether the matrix-core schedule is expected to beat the vector one for Q
+// queries against C chunks of dimension d.  Relative costs per (limb, slot),
+// from the kernels' times at Q = 64, C = 123, d = 128: the 64-bit vector
+// multiply-accumulate 8.6 ms (scales with Q C d); the matrix-core path's
+// digit transpose 1.35 ms (Q Dp), MFMA tiles 2.4 ms (64-row x 64-chunk tiles
+// x Dp, 4 of them) and sums transpose 1.25 ms (Q C).
+bool mfma_expected_faster(uint32_t Q, uint32_t C, uint32_t d) {
+  const double Dp = mfma_padded_d((int)d);
+  const double valu = 8.6 * (double)Q * C * d / (64.0 * 123 * 128);
+  const double tiles = (double)((2 * Q + 63) / 64) * ((C + 63) / 64);
+  const double mfma = 1.35 * Q * Dp / (64.0 * 128) + 2.4 * tiles * Dp / (4.0 * 128) +
+                      1.25 * (double)Q * C / (64.0 * 123);
+  return mfma < valu;
+}
+
+// Whether an all-pairs (or not) call of Q queries against C chunks runs the
+// matrix-core schedule: forced by sanns_set_schedule, or chosen by default on
+// a digit database when the cost model predicts it faster.
+bool call_uses_mfma(const sanns_ctx* ctx, uint32_t Q, uint32_t C, uint32_t d, bool all_pairs) {
+  if (!all_pairs || Q < 2 || !db_has_digits(ctx, d)) return false;
+  if (ctx->force_lds > 0) return ctx->force_lds == kMfmaSchedule;
+  return mfma_expected_faster(Q, C, d);
+}
+
+void choose_shape(const sanns_ctx* ctx, uint32_t Q, uint32_t C, uint32_t d, bool regular,
+                  double q_per_chunk, int& qt, int& ct, int& lds) {
   lds = 0;
   if (regular && Q >= 2) {
-    if (ctx->force_lds > 0)
-      lds = ctx->force_lds;
+    if (call_uses_mfma(ctx, Q, C, d, true))
+      lds = kMfmaSchedule;
     else
-      lds = db_has_digits(ctx, d) ? kMfmaSchedule : kDefaultLdsVariant;
+      lds = ctx->force_lds > 0 ? ctx->force_lds : kDefaultLdsVariant;
     if (lds == kMfmaSchedule && !db_has_digits(ctx, d)) lds = kDefaultLdsVariant;
     if (lds != kMfmaSchedule && (int)ctx->p.N % mac_lds_min_n(lds) != 0) lds = 0;
   }
@@ -230,7 +254,8 @@ struct WsLayout {
   size_t qntt, tiles, work, tmp, ctrl, qdig, sums, total;
 };
 
-WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M) {
+// mfma: the call runs the matrix-core schedule (query digits and sums regions).
+WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M, bool mfma) {
   const size_t N = ctx->p.N, L = ctx->p.L;
   WsLayout w;
   size_t off = 0;
@@ -245,7 +270,7 @@ WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M) {
   w.ctrl = off;  // control words of the persistent schedule
   off += align256(kPersistCtrlWords * sizeof(uint32_t));
   w.qdig = w.sums = off;
-  if (ctx->digit_db && mfma_supported(ctx->logN, (int)d)) {
+  if (mfma) {
     // matrix-core schedule: query digits and slot-major sums (all pairs: C = M / Q)
     off += align256(L * N * 2 * Q * 7 * (size_t)mfma_padded_d((int)d));
     w.sums = off;
@@ -528,9 +553,11 @@ extern "C" sanns_status sanns_decrypt_shares(sanns_ctx* ctx, const int8_t* sk,
 
 extern "C" size_t sanns_distances_workspace(const sanns_ctx* ctx, const sanns_db* db,
                                             uint32_t Q, uint32_t M, int mode) {
-  (void)mode;
   if (!ctx || !db) return 0;
-  return ws_layout(ctx, db->d, Q, M).total;
+  const bool mfma = mode != SANNS_MODE_PERSISTENT && mode != SANNS_MODE_PLAIN && Q > 0 &&
+                    (uint64_t)M == (uint64_t)Q * db->n_chunks &&
+                    call_uses_mfma(ctx, Q, db->n_chunks, db->d, true);
+  return ws_layout(ctx, db->d, Q, M, mfma).total;
 }
 
 namespace {
@@ -663,7 +690,9 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
       if (work[2 * m] >= Q || work[2 * m + 1] >= C)
         return fail(SANNS_E_RANGE, "work[%u] = (%u, %u) outside Q x n_chunks", m, work[2 * m],
                     work[2 * m + 1]);
-  const WsLayout W = ws_layout(ctx, db->d, Q, M);
+  const bool mfma = mode != SANNS_MODE_PERSISTENT && mode != SANNS_MODE_PLAIN &&
+                    call_uses_mfma(ctx, Q, C, db->d, work == nullptr);
+  const WsLayout W = ws_layout(ctx, db->d, Q, M, mfma);
   if (ws_bytes < W.total)
     return fail(SANNS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, W.total);
   HIP_TRY(hipSetDevice(ctx->device));
@@ -712,7 +741,7 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
     return fail(SANNS_E_INVALID,
                 "the matrix-core schedule needs SANNS_FLAG_DIGIT_DB, N >= 64 and d <= %d",
                 kMfmaMaxD);
-  choose_shape(ctx, Q, db->d, work == nullptr, q_per_chunk, qt, ct, lds);
+  choose_shape(ctx, Q, C, db->d, work == nullptr, q_per_chunk, qt, ct, lds);
   if (pshape) {
     qt = kPersistTileQ;
     ct = kPersistTileC;

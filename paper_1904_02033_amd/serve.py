@@ -106,9 +106,13 @@ class Server:
         self.inflight: List[_Launch] = []
         self.keep_outputs = keep_outputs
         self.streams = [torch.cuda.Stream() for _ in range(max_inflight)]
-        # per launch slot: reusable workspace and query staging buffers
+        # per launch slot: reusable workspace, query staging and (when outputs
+        # are released at completion) output buffers, grown geometrically so
+        # that steady-state serving allocates nothing
         self.pool_ws: List[Optional[torch.Tensor]] = [None] * max_inflight
         self.pool_ct: List[Optional[torch.Tensor]] = [None] * max_inflight
+        self.pool_out: List[Optional[torch.Tensor]] = [None] * max_inflight
+        self.pool_share: List[Optional[torch.Tensor]] = [None] * max_inflight
         self.busy = [False] * max_inflight
         self.used = 0
         self.peak_used = 0
@@ -214,10 +218,16 @@ class Server:
             self._launch(dbname, st, jobs)
 
     def _grow(self, pool: list, slot: int, nbytes: int, like: torch.Tensor) -> torch.Tensor:
+        """The slot's buffer, reallocated (at least doubled, at least 64 MiB)
+        when it is smaller than nbytes: a handful of allocations per pool
+        over a run, so the caching allocator is not fragmented by buffers of
+        every size."""
         buf = pool[slot]
         if buf is None or buf.numel() < nbytes:
-            buf = torch.empty(max(nbytes, int(1.25 * (0 if buf is None else buf.numel()))),
-                              dtype=torch.uint8, device=like.device)
+            old = 0 if buf is None else buf.numel()
+            pool[slot] = None
+            buf = torch.empty(max(nbytes, 2 * old, 64 << 20), dtype=torch.uint8,
+                              device=like.device)
             pool[slot] = buf
         return buf
 
@@ -252,8 +262,13 @@ class Server:
                                                  ct.shape[0] * desc_db.n_chunks
                                                  if work is None else len(work), self.mode)
             ws = self._grow(self.pool_ws, slot, need, ct)
+            outs = None
+            if not self.keep_outputs:
+                M = ct.shape[0] * desc_db.n_chunks if work is None else len(work)
+                outs = (self._grow(self.pool_out, slot, M * 2 * R.ctx.L * R.ctx.N * 8, ct),
+                        self._grow(self.pool_share, slot, M * R.ctx.N * 4, ct))
             D = stage.Distances(R.ctx, desc_db, ct.shape[0], work=work, mode=self.mode,
-                                workspace=ws)
+                                workspace=ws, out_buffers=outs)
             out, share = D.run(ct, key, qd, stream)
             ev = torch.cuda.Event()
             ev.record(stream)

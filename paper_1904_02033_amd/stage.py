@@ -134,9 +134,12 @@ class Distances:
 
     def __init__(self, ctx: Context, db: Database, Q: int,
                  work: Optional[np.ndarray] = None, mode: int = nat.SANNS_MODE_FUSED,
-                 workspace: Optional[torch.Tensor] = None):
+                 workspace: Optional[torch.Tensor] = None,
+                 out_buffers: Optional[tuple] = None):
         """workspace: optional uint8 device tensor of at least the required
-        size, reused instead of a fresh allocation."""
+        size, reused instead of a fresh allocation; out_buffers: optional
+        pair of uint8 device tensors that hold the ciphertext outputs and the
+        shares (at least M 2 L N 8 and M N 4 bytes), likewise reused."""
         self.ctx, self.db, self.Q, self.mode = ctx, db, Q, mode
         self.work = None if work is None else np.ascontiguousarray(work, dtype=np.uint32)
         self.M = Q * db.n_chunks if work is None else len(self.work)
@@ -146,8 +149,16 @@ class Distances:
             self.ws = workspace[:self.ws_bytes]
         else:
             self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
-        self.ct_out = torch.empty((self.M, 2, ctx.L, ctx.N), dtype=torch.uint64, device=dev)
-        self.share = torch.empty((self.M, ctx.N), dtype=torch.uint32, device=dev)
+        shape_out, shape_share = (self.M, 2, ctx.L, ctx.N), (self.M, ctx.N)
+        if out_buffers is not None:
+            nb_out, nb_share = self.M * 2 * ctx.L * ctx.N * 8, self.M * ctx.N * 4
+            if out_buffers[0].numel() < nb_out or out_buffers[1].numel() < nb_share:
+                raise ValueError("output buffers are too small")
+            self.ct_out = out_buffers[0][:nb_out].view(torch.uint64).view(shape_out)
+            self.share = out_buffers[1][:nb_share].view(torch.uint32).view(shape_share)
+        else:
+            self.ct_out = torch.empty(shape_out, dtype=torch.uint64, device=dev)
+            self.share = torch.empty(shape_share, dtype=torch.uint32, device=dev)
 
     def run(self, ct_in: torch.Tensor, mask_key: bytes, query_ids: torch.Tensor,
             stream=None):
