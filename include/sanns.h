@@ -285,14 +285,15 @@ sanns_status sanns_device_status(sanns_ctx *ctx, void *stream);
 sanns_status sanns_set_schedule(sanns_ctx *ctx, int lds_variant, int qt, int ct);
 
 /* Phases timed by the profiler, in launch order. */
-#define SANNS_PHASE_QUERY_NTT 0 /* forward NTT of the query ciphertexts
-                                   (and, SANNS_SCHEDULE_MFMA, their digits) */
+#define SANNS_PHASE_QUERY_NTT 0 /* forward NTT of the query ciphertexts     */
 #define SANNS_PHASE_MASKS 1     /* ChaCha20 masks -> server shares          */
 #define SANNS_PHASE_MAC 2       /* multiply-accumulate over the database    */
-#define SANNS_PHASE_INTT_MASK 3 /* INTT + Delta [||p||^2 - r]_t (and,
-                                   SANNS_SCHEDULE_MFMA, the transpose of the
-                                   slot-major sums before it)               */
-#define SANNS_N_PHASES 4
+#define SANNS_PHASE_INTT_MASK 3 /* INTT + Delta [||p||^2 - r]_t             */
+#define SANNS_PHASE_DIGITS 4    /* SANNS_SCHEDULE_MFMA: query NTT form ->
+                                   signed digits (0 for other schedules)    */
+#define SANNS_PHASE_SUMS 5      /* SANNS_SCHEDULE_MFMA: slot-major sums ->
+                                   NTT-form outputs (0 for other schedules) */
+#define SANNS_N_PHASES 6
 
 /* Per-phase timing of the fused form (tracing aid).  While enabled,
  * sanns_distances in SANNS_MODE_FUSED or SANNS_MODE_BATCHED records a HIP
@@ -303,7 +304,7 @@ sanns_status sanns_set_schedule(sanns_ctx *ctx, int lds_variant, int qt, int ct)
 sanns_status sanns_profile_enable(sanns_ctx *ctx, int on);
 
 /* Synchronise on the recorded events and write, for each phase, the mean
- * duration in milliseconds over the calls since enabling (ms_out[4], host)
+ * duration in milliseconds over the calls since enabling (ms_out[SANNS_N_PHASES], host)
  * and the number of calls (*calls, host, may be NULL). */
 sanns_status sanns_profile_read(sanns_ctx *ctx, double *ms_out, int *calls);
 

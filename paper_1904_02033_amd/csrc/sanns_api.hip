@@ -417,7 +417,7 @@ extern "C" sanns_status sanns_profile_enable(sanns_ctx* ctx, int on) {
 extern "C" sanns_status sanns_profile_read(sanns_ctx* ctx, double* ms_out, int* calls) {
   if (!ctx || !ms_out) return fail(SANNS_E_INVALID, "null argument");
   std::lock_guard<std::mutex> lock(ctx->mu);
-  double sum[SANNS_N_PHASES] = {0, 0, 0, 0};
+  double sum[SANNS_N_PHASES] = {};
   for (auto& call : ctx->prof_events)
     for (int p = 0; p < SANNS_N_PHASES; ++p) {
       HIP_TRY(hipEventSynchronize(call[p].second));
@@ -588,9 +588,11 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
   HIP_TRY(mark(SANNS_PHASE_QUERY_NTT, false));
   HIP_TRY(launch_ntt_fwd(ct_in, qntt, (int)(Q * d * 2 * L), ctx->logN, (int)L, ctx->ps,
                          ctx->tws, ctx->d_err, mfma ? 2 : 1, st, (int)d, (int)(2 * Q)));
+  HIP_TRY(mark(SANNS_PHASE_QUERY_NTT, true));
+  HIP_TRY(mark(SANNS_PHASE_DIGITS, false));
   if (mfma)
     HIP_TRY(launch_query_digits(qntt, qdig, (int)Q, (int)d, (int)L, ctx->logN, st));
-  HIP_TRY(mark(SANNS_PHASE_QUERY_NTT, true));
+  HIP_TRY(mark(SANNS_PHASE_DIGITS, true));
   HIP_TRY(mark(SANNS_PHASE_MASKS, false));
   HIP_TRY(launch_masks(K, qids, dwork, (int)C, (int)M, ctx->logN, (uint32_t)ctx->p.t, ctx->tone,
                        share, st));
@@ -607,9 +609,11 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
     HIP_TRY(launch_mac(qt, ct, (const uint2*)qntt, res, dtiles, n_tiles, (int)Q, (int)d, (int)L,
                        ctx->logN, (int)C, ctx->ps, ct_out, st));
   HIP_TRY(mark(SANNS_PHASE_MAC, true));
-  HIP_TRY(mark(SANNS_PHASE_INTT_MASK, false));
+  HIP_TRY(mark(SANNS_PHASE_SUMS, false));
   if (mfma)
     HIP_TRY(launch_sums_to_ct(sums, ct_out, (int)Q, (int)C, (int)L, ctx->logN, ctx->ps, st));
+  HIP_TRY(mark(SANNS_PHASE_SUMS, true));
+  HIP_TRY(mark(SANNS_PHASE_INTT_MASK, false));
   HIP_TRY(launch_intt_mask(ct_out, share, norms, dwork, (int)C, (int)M, ctx->logN, (int)L,
                            (uint32_t)ctx->p.t, ctx->ps, ctx->tws, st));
   HIP_TRY(mark(SANNS_PHASE_INTT_MASK, true));

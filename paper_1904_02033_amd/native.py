@@ -41,8 +41,8 @@ EXPORTS = [
     "sanns_distances", "sanns_device_status", "sanns_set_schedule",
     "sanns_profile_enable", "sanns_profile_read",
 ]
-SANNS_N_PHASES = 4
-PHASES = ["query_ntt", "masks", "mac", "intt_mask"]
+SANNS_N_PHASES = 6
+PHASES = ["query_ntt", "masks", "mac", "intt_mask", "query_digits", "sums_transpose"]
 
 
 class SannsError(RuntimeError):

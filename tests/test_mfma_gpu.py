@@ -171,3 +171,26 @@ def test_mfma_default_and_limits(stage):
     ctx.device_status()
     want = oracle.masks(wide.key, int(wide.qids[1]), 0, wide.P.t, wide.N)
     assert (share[1].cpu().numpy() == want).all()
+
+
+def test_profile_phases_split_by_schedule(stage):
+    """Per-phase timing: the matrix-core schedule reports its digit and sums
+    transposes as phases of their own; the vector schedule leaves them 0."""
+    from paper_1904_02033_amd import native as nat
+    pb = make_problem(8192, 3, 26, 3 * 8192, 64, 8, "u8", seed=7)
+    ctx, db, sk, ct, qids = _setup(stage, pb)
+    for variant, extra in ((MFMA, True), (22, False)):
+        ctx.set_schedule(0, 0, variant)
+        D = stage.Distances(ctx, db, pb.Q, None, nat.SANNS_MODE_BATCHED)
+        D.run(ct, pb.key, qids)
+        nat.sanns_profile_enable(ctx.handle, True)
+        for _ in range(2):
+            D.run(ct, pb.key, qids)
+        ph, calls = nat.sanns_profile_read(ctx.handle)
+        nat.sanns_profile_enable(ctx.handle, False)
+        ctx.device_status()
+        assert calls == 2 and set(ph) == set(nat.PHASES)
+        for k in ("query_ntt", "masks", "mac", "intt_mask"):
+            assert ph[k] > 0, (variant, k)
+        for k in ("query_digits", "sums_transpose"):
+            assert (ph[k] > 0) == extra or (not extra and ph[k] < 0.05), (variant, k, ph[k])
