@@ -47,6 +47,7 @@ constexpr size_t kMfmaDbSlack = 64 * 1024;
 constexpr int vmcnt_wait(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
 constexpr int kWaitAllVmem = vmcnt_wait(0);
 constexpr int kWaitAllBut7Vmem = vmcnt_wait(7);
+constexpr int kWaitAllBut8Vmem = vmcnt_wait(8);
 constexpr int kWaitAllBut14Vmem = vmcnt_wait(14);
 
 // The signed digits of x < 2^54 as the bytes of a word (byte 7 is zero).
@@ -151,15 +152,38 @@ __device__ __forceinline__ uint64_t fold_digit_sums(const int32_t (&S)[13],
          shoup_approx(x2, D.w64, D.w64p, D.nq);  // < 2^55 + 8q < 2^58
 }
 
+// LDS byte address of a shared-memory pointer.
+__device__ __forceinline__ uint32_t lds_address(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// The 16-byte fragments of the 7 digit rows (DP bytes apart) of one column
+// tile and step, read in one asm block that waits for its own reads before
+// it ends (its outputs are never written behind the compiler's back).
+template <int DP>
+__device__ __forceinline__ void lds_frags(uint32_t addr, v4i (&bf)[7]) {
+  asm volatile(
+      "ds_read_b128 %0, %7\n\t"
+      "ds_read_b128 %1, %7 offset:%8\n\t"
+      "ds_read_b128 %2, %7 offset:%9\n\t"
+      "ds_read_b128 %3, %7 offset:%10\n\t"
+      "ds_read_b128 %4, %7 offset:%11\n\t"
+      "ds_read_b128 %5, %7 offset:%12\n\t"
+      "ds_read_b128 %6, %7 offset:%13\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(bf[0]), "=&v"(bf[1]), "=&v"(bf[2]), "=&v"(bf[3]), "=&v"(bf[4]), "=&v"(bf[5]),
+        "=&v"(bf[6])
+      : "v"(addr), "n"(DP), "n"(2 * DP), "n"(3 * DP), "n"(4 * DP), "n"(5 * DP), "n"(6 * DP));
+}
+
 // One workgroup: 64 rows x 64 chunks of kMfmaSlots consecutive slots of one
 // limb, the chunks taken as two halves of 32 that reuse the same query
 // fragments.  Wave w owns rows 16w .. 16w + 15 of the tile and the two
 // 16-chunk column tiles of the current half; its query fragments come
 // straight from global memory into registers, the half's database digits are
 // staged in LDS by DMA (global_load_lds): a slot's first half in sb0, its
-// second in sb1.  A DMA is issued once the MFMAs of the half before it have
-// read their buffer (an LDS read is not issued while a DMA into LDS is in
-// flight) and lands while that half's sums are folded.  Every memory
+// second in sb1.  The DMA into one buffer is issued at the start of the half
+// that multiplies the other, so it lands behind that half's MFMAs.  Every memory
 // operation of the slot loop is unconditional (the digit region has slack
 // past its end, the sums buffer is padded to whole tiles), so the loop body is
 // straight-line code whose memory counters the compiler tracks exactly.
@@ -217,18 +241,23 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
   // 98 MFMAs of one step: every digit pair (a, b) of both column tiles into
   // diagonal a + b; the first product of a diagonal starts from a zero
   // accumulator (b = 0, or a = 6 for the diagonals above 6).
-  auto mfma_step = [&](const v4i (&af)[7], int ks, const int8_t* bbase, v4i (&acc)[2][13]) {
+  // The 7 database fragments of a column tile are read by lds_frags (one
+  // asm block with its own wait: the compiler, which cannot tell the two
+  // staging buffers apart, would otherwise hold every LDS read until a DMA
+  // into the other buffer has landed).
+  auto mfma_step = [&](const v4i (&af)[7], int ks, uint32_t bbase, v4i (&acc)[2][13]) {
 #pragma unroll
-    for (int b = 0; b < 7; ++b)
+    for (int cs = 0; cs < 2; ++cs) {
+      v4i bf[7];
+      lds_frags<Dp>(bbase + cs * 16 * Sk + 64 * ks, bf);
 #pragma unroll
-      for (int cs = 0; cs < 2; ++cs) {
-        const v4i bf = *reinterpret_cast<const v4i*>(bbase + cs * 16 * Sk + b * Dp + 64 * ks);
+      for (int b = 0; b < 7; ++b)
 #pragma unroll
         for (int a = 0; a < 7; ++a)
           acc[cs][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-              af[a], bf, (ks == 0 && (b == 0 || a == 6)) ? v4i{0, 0, 0, 0} : acc[cs][a + b], 0,
-              0, 0);
-      }
+              af[a], bf[b],
+              (ks == 0 && (b == 0 || a == 6)) ? v4i{0, 0, 0, 0} : acc[cs][a + b], 0, 0, 0);
+    }
   };
   // Fold of the accumulators of one half into sums below 2^58.
   auto fold = [&](const v4i (&acc)[2][13], uint64_t (&v)[2][4]) {
@@ -252,8 +281,8 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
       for (int e = 0; e < 4; ++e) dst[(size_t)e * Cp + 16 * cs] = v[cs][e];
   };
 
-  const int8_t* b0 = reinterpret_cast<const int8_t*>(sb0) + m16 * Sk + 16 * g;
-  const int8_t* b1 = reinterpret_cast<const int8_t*>(sb1) + m16 * Sk + 16 * g;
+  const uint32_t b0 = lds_address(sb0) + m16 * Sk + 16 * g;
+  const uint32_t b1 = lds_address(sb1) + m16 * Sk + 16 * g;
   v4i a0[7], a1[7];
   stage(p0, 0, sb0);
   load_a(p0, 0, a0);
@@ -265,12 +294,15 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
     // the last slot restages itself (keeps the body uniform)
     const int pn = jj + 1 < kMfmaSlots ? p + 1 : p;
     uint64_t v[2][4];
-    {  // first half: chunks k0 .. k0 + 31 from sb0; then the second half's DMA
+    {  // first half: chunks k0 .. k0 + 31 from sb0, the second half's DMA into sb1
+      // the slot's query fragments (older than the previous half's 8 stores)
+      __builtin_amdgcn_s_waitcnt(kWaitAllBut8Vmem);
+      __builtin_amdgcn_sched_barrier(0);
+      stage(p, 1, sb1);
+      __builtin_amdgcn_sched_barrier(0);
       v4i acc[2][13];
       mfma_step(a0, 0, b0, acc);
       if (NKS == 2) mfma_step(a1, 1, b0, acc);
-      __builtin_amdgcn_sched_barrier(0);
-      stage(p, 1, sb1);
       __builtin_amdgcn_sched_barrier(0);
       fold(acc, v);
       __builtin_amdgcn_sched_barrier(0);
@@ -279,7 +311,9 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
       __builtin_amdgcn_s_barrier();
       store(p, 0, v);
     }
-    {  // second half from sb1; then the next slot's first half and fragments
+    {  // second half from sb1, the next slot's first half into sb0, its fragments
+      stage(pn, 0, sb0);
+      __builtin_amdgcn_sched_barrier(0);
       v4i acc[2][13];
       mfma_step(a0, 0, b1, acc);
       __builtin_amdgcn_sched_barrier(0);
@@ -288,16 +322,15 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
         __builtin_amdgcn_sched_barrier(0);
         mfma_step(a1, 1, b1, acc);
         __builtin_amdgcn_sched_barrier(0);
-        stage(pn, 0, sb0);
         load_a(pn, 1, a1);  // step 1 of the next slot, during the fold
       } else {
-        stage(pn, 0, sb0);
         load_a(pn, 0, a0);
       }
       __builtin_amdgcn_sched_barrier(0);
       fold(acc, v);
       __builtin_amdgcn_sched_barrier(0);
-      __builtin_amdgcn_s_waitcnt(kWaitAllBut7Vmem);  // the DMA into sb0
+      // the DMA into sb0 (older than the newest 7 fragment loads per step)
+      __builtin_amdgcn_s_waitcnt(NKS == 2 ? kWaitAllBut14Vmem : kWaitAllBut7Vmem);
       __builtin_amdgcn_sched_barrier(0);
       __builtin_amdgcn_s_barrier();
       store(p, 1, v);
