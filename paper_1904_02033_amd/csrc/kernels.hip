@@ -70,7 +70,8 @@ __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
       const int s = ntt_slot<LOGN>(tid, a);
-      base[(size_t)(s >> 5) * d * 32 + (s & 31)] = v[a];
+      // read once, by the digit transpose
+      __builtin_nontemporal_store(v[a], base + (size_t)(s >> 5) * d * 32 + (s & 31));
     }
   } else if (split) {
     uint2* dst2 = reinterpret_cast<uint2*>(dst);

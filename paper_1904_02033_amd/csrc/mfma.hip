@@ -38,6 +38,7 @@ constexpr int kMfmaRows = 64;    // rows per workgroup: 4 waves x 16
 constexpr int kMfmaChunks = 64;  // chunks per workgroup: 2 halves of 2 MFMA column tiles
 constexpr int kMfmaSlots = 8;    // consecutive slots per workgroup
 constexpr int kDigitSlots = 32;  // slots per workgroup of the digit transposes
+constexpr int kDigitThreads = 512;
 // The database digit region ends with this many spare bytes: a staged half
 // tile may run past the last chunk (at most 32 chunks of at most 7 x 128 + 16
 // bytes each, plus one DMA round of 256 x 16 bytes).
@@ -69,9 +70,11 @@ __device__ __forceinline__ uint32_t gather_byte(uint64_t y0, uint64_t y1, uint64
 // workgroup's d x 32 words are one contiguous block) or a database chunk
 // (source: the database residues [L][C][d][N] as 27-bit halves), stages the
 // words in LDS, and writes each slot's 7 digit rows of Dp bytes (16 bytes per
-// store, zero digits past coordinate d).
+// store, zero digits past coordinate d; two threads share a slot's
+// 16-coordinate group, one for digits 0-3, one for 4-6).  The query side is
+// read and written with nontemporal hints: it is touched once.
 template <bool DB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kDigitThreads)
 k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, int d, int Dp,
             int L, int logN, int C, int Sk) {
   extern __shared__ uint64_t lw[];  // [Dp][kDigitSlots + 1]
@@ -84,7 +87,7 @@ k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, i
   const int ent = b % n_ent, l = b / n_ent;
   const int p0 = pg * kDigitSlots;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < Dp * kDigitSlots; idx += 256) {
+  for (int idx = tid; idx < Dp * kDigitSlots; idx += kDigitThreads) {
     const int i = idx / kDigitSlots, pp = idx % kDigitSlots;
     uint64_t x = 0;
     if (i < d) {
@@ -93,16 +96,17 @@ k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, i
             src)[(((size_t)l * C + ent) * d + i) * N + p0 + pp];
         x = (uint64_t)h.x + ((uint64_t)h.y << 27);
       } else {
-        x = reinterpret_cast<const uint64_t*>(
-            src)[(((size_t)l * n_ent + ent) * groups + pg) * d * kDigitSlots + idx];
+        x = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(
+            src) + (((size_t)l * n_ent + ent) * groups + pg) * d * kDigitSlots + idx);
       }
     }
     lw[i * P1 + pp] = digit_word(x);
   }
   __syncthreads();
   const int cg_n = Dp / 16;
-  for (int u = tid; u < kDigitSlots * cg_n; u += 256) {
-    const int cg = u % cg_n, pp = u / cg_n;
+  typedef unsigned v4u __attribute__((ext_vector_type(4)));
+  for (int u = tid; u < 2 * kDigitSlots * cg_n; u += kDigitThreads) {
+    const int hf = u & 1, cg = (u >> 1) % cg_n, pp = (u >> 1) / cg_n;
     const int p = p0 + pp;
     uint64_t y[16];
 #pragma unroll
@@ -110,15 +114,17 @@ k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, i
     int8_t* row = DB ? dst + (((size_t)l * N + p) * C + ent) * Sk
                      : dst + (((size_t)l * N + p) * n_ent + ent) * (size_t)(7 * Dp);
 #pragma unroll
-    for (int a = 0; a < 7; ++a) {
-      uint4 v;
+    for (int aa = 0; aa < 4; ++aa) {
+      const int a = hf ? 4 + aa : aa;
+      if (a > 6) break;
+      v4u v;
       v.x = gather_byte(y[0], y[1], y[2], y[3], a);
       v.y = gather_byte(y[4], y[5], y[6], y[7], a);
       v.z = gather_byte(y[8], y[9], y[10], y[11], a);
       v.w = gather_byte(y[12], y[13], y[14], y[15], a);
-      *reinterpret_cast<uint4*>(row + a * Dp + 16 * cg) = v;
+      __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(row + a * Dp + 16 * cg));
     }
-    if (DB && cg == 0) *reinterpret_cast<uint4*>(row + 7 * Dp) = make_uint4(0, 0, 0, 0);
+    if (DB && cg == 0 && hf == 0) *reinterpret_cast<uint4*>(row + 7 * Dp) = make_uint4(0, 0, 0, 0);
   }
 }
 
@@ -400,7 +406,7 @@ hipError_t launch_query_digits(const uint64_t* qntt, int8_t* qd, int Q, int d, i
   const long nb = (long)L * 2 * Q * (N / kDigitSlots);
   if (nb <= 0) return hipSuccess;
   const size_t lds = (size_t)Dp * (kDigitSlots + 1) * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_to_digits<false>, dim3((unsigned)nb), dim3(256), lds, st,
+  hipLaunchKernelGGL(k_to_digits<false>, dim3((unsigned)nb), dim3(kDigitThreads), lds, st,
                      (const void*)qntt, qd, 2 * Q, d, Dp, L, logN, 0, 0);
   return hipGetLastError();
 }
@@ -411,7 +417,7 @@ hipError_t launch_db_digits(const uint2* dbres, int8_t* dbd, int C, int d, int L
   const long nb = (long)L * C * (N / kDigitSlots);
   if (nb <= 0) return hipSuccess;
   const size_t lds = (size_t)Dp * (kDigitSlots + 1) * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_to_digits<true>, dim3((unsigned)nb), dim3(256), lds, st,
+  hipLaunchKernelGGL(k_to_digits<true>, dim3((unsigned)nb), dim3(kDigitThreads), lds, st,
                      (const void*)dbres, dbd, C, d, Dp, L, logN, C, mfma_db_stride(d));
   return hipGetLastError();
 }
