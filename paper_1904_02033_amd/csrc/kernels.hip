@@ -43,13 +43,12 @@ __device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, const Prime& 
 //      r = 2q + c (R = 2Q) for polynomial p = ((q d + i) 2 + c) L + l: each
 //      32-slot group of a row is one contiguous block over the coordinates,
 //      the form the digit transpose of the matrix-core schedule reads.
-template <int LOGN>
+template <int LOGN, int SPLIT>
 __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
                                              const uint64_t* __restrict__ in,
                                              uint64_t* __restrict__ out, int L,
                                              const PrimeSet& ps, const TwSet& tws,
-                                             uint32_t* err, int split, int d = 0,
-                                             int R = 0) {
+                                             uint32_t* err, int d = 0, int R = 0) {
   constexpr int N = NttShape<LOGN>::N;
   const int l = p % L;
   const Prime& P = ps.p[l];
@@ -64,7 +63,7 @@ __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
   if (bad && err) atomicOr(err, 1u);
   ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P);
   uint64_t* dst = out + (size_t)p * N;
-  if (split == 2) {
+  if constexpr (SPLIT == 2) {
     const int c = (p / L) & 1, i = (p / (2 * L)) % d, q = p / (2 * L * d);
     uint64_t* base = out + (((size_t)l * R + 2 * q + c) * (N / 32) * d + i) * 32;
 #pragma unroll
@@ -73,7 +72,7 @@ __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
       // read once, by the digit transpose
       __builtin_nontemporal_store(v[a], base + (size_t)(s >> 5) * d * 32 + (s & 31));
     }
-  } else if (split) {
+  } else if constexpr (SPLIT == 1) {
     uint2* dst2 = reinterpret_cast<uint2*>(dst);
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
@@ -87,13 +86,26 @@ __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
   }
 }
 
+// Waves per SIMD the transform kernels are compiled for: the largest of 4,
+// 6 and 8 at which the compiler fits them in registers without spilling
+// (checked for every log2 N).  The forward needs 64-72 registers; at eight
+// waves (64 registers) the digit form fits except for log2 N = 8, 9 and 14,
+// the other forms do not.  The inverse with the mask needs 110-128 registers
+// at four waves and 75-80 at six, spilling at six for log2 N = 11, 12, 14.
+constexpr int ntt_fwd_waves(int logn, int split) {
+  return split == 2 && logn != 8 && logn != 9 && logn != 14 ? 8 : 6;
+}
+constexpr int intt_mask_waves(int logn) {
+  return logn == 11 || logn == 12 || logn == 14 ? 4 : 6;
+}
+
 // One polynomial per workgroup.
-template <int LOGN>
-__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
+template <int LOGN, int SPLIT>
+__global__ void __launch_bounds__(NttShape<LOGN>::T, ntt_fwd_waves(LOGN, SPLIT))
 k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int L, PrimeSet ps,
-          TwSet tws, uint32_t* err, int split, int d, int R) {
+          TwSet tws, uint32_t* err, int d, int R) {
   extern __shared__ uint64_t lds[];
-  ntt_fwd_poly<LOGN>(blockIdx.x, threadIdx.x, lds, in, out, L, ps, tws, err, split, d, R);
+  ntt_fwd_poly<LOGN, SPLIT>(blockIdx.x, threadIdx.x, lds, in, out, L, ps, tws, err, d, R);
 }
 
 // In-place inverse transform, result multiplied by N^-1 and in [0, q).
@@ -235,8 +247,10 @@ __device__ __forceinline__ void intt_mask_poly(int p, int tid, uint64_t* lds,
   for (int a = 0; a < 16; ++a) buf[coef_index<LOGN>(tid, a)] = v[a];
 }
 
+// At N = 8192: six waves per SIMD (78 registers, three workgroups of 512
+// threads per CU) run 8% faster than four (126 registers, two workgroups).
 template <int LOGN>
-__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
+__global__ void __launch_bounds__(NttShape<LOGN>::T, intt_mask_waves(LOGN))
 k_intt_mask(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
             const uint32_t* __restrict__ norms, const uint32_t* __restrict__ work, int C,
             int L, uint32_t t, PrimeSet ps, TwSet tws) {
@@ -876,7 +890,7 @@ k_persistent(PersistArgs A, PrimeSet ps, TwSet tws) {
     const int tk = s_ticket;
     if (tk >= n1) break;
     if (tk < n_ntt) {
-      ntt_fwd_poly<LOGN>(tk, tid, lds, A.ct_in, A.qntt, L, ps, tws, A.err, 1);
+      ntt_fwd_poly<LOGN, 1>(tk, tid, lds, A.ct_in, A.qntt, L, ps, tws, A.err);
       ++done_ntt;
     } else {
       const int m = tk - n_ntt;
@@ -1278,10 +1292,14 @@ hipError_t launch_ntt_fwd(const uint64_t* in, uint64_t* out, int n_polys, int lo
   if (n_polys <= 0) return hipSuccess;
   if (split == 2 && (logN < 5 || d <= 0 || n_polys != R * d * L)) return hipErrorInvalidValue;
   switch (logN) {
-#define SANNS_CASE(LG)                                                                 \
-  case LG:                                                                             \
-    ntt_launch<LG>(k_ntt_fwd<LG>, (unsigned)n_polys, st, in, out, L, ps, tws, err, split, \
-                   d, R);                                                              \
+#define SANNS_CASE(LG)                                                                    \
+  case LG:                                                                                \
+    if (split == 2)                                                                       \
+      ntt_launch<LG>(k_ntt_fwd<LG, 2>, (unsigned)n_polys, st, in, out, L, ps, tws, err, d, R); \
+    else if (split == 1)                                                                  \
+      ntt_launch<LG>(k_ntt_fwd<LG, 1>, (unsigned)n_polys, st, in, out, L, ps, tws, err, d, R); \
+    else                                                                                  \
+      ntt_launch<LG>(k_ntt_fwd<LG, 0>, (unsigned)n_polys, st, in, out, L, ps, tws, err, d, R); \
     break;
     SANNS_LOGN_CASES(SANNS_CASE)
 #undef SANNS_CASE

@@ -25,7 +25,8 @@
 // bits [lo, lo + B) a thread holds the 16 residues whose index has its thread
 // id (and, when B < 4, 4 - B extra bits from the register slot) in the other
 // bit positions; the B stages run in registers and passes exchange data
-// through LDS, padded by one word per 16 against bank collisions.
+// through LDS (in two 32-bit halves), padded by one word per 16 against bank
+// collisions.
 //
 // Global layouts that follow:
 //   coefficient form: slot a of thread tid holds coefficient coef_index(tid, a),
@@ -49,7 +50,8 @@ struct NttShape {
   static constexpr int fwd_b(int j) { return j == 0 ? R : 4; }
   static constexpr int inv_lo(int j) { return 4 * j; }
   static constexpr int inv_b(int j) { return j == P - 1 ? R : 4; }
-  static constexpr size_t lds_bytes = (size_t)(N + (N >> 4)) * sizeof(uint64_t);
+  // exchanges go through LDS in two 32-bit halves
+  static constexpr size_t lds_bytes = (size_t)(N + (N >> 4)) * sizeof(uint32_t);
 };
 
 __device__ __forceinline__ constexpr int lds_pad(int idx) { return idx + (idx >> 4); }
@@ -156,18 +158,32 @@ __device__ __forceinline__ void inv_pass(uint64_t (&v)[16], int tid,
   }
 }
 
-template <int LOGN, int B, int LO>
-__device__ __forceinline__ void lds_store(const uint64_t (&v)[16], uint64_t* lds, int tid) {
-  uint64_t* base = lds + lds_pad(eidx<LOGN, B, LO>(tid, 0));
+// Exchange between a pass over bits [LO0, LO0 + B0) and one over
+// [LO1, LO1 + B1): every residue is written at its index and read back by the
+// thread that holds that index in the next pass.  The words go through LDS
+// as two 32-bit halves, so the buffer is N + N/16 32-bit words (a third
+// workgroup of N/16 threads fits beside two others); the barrier between the
+// halves keeps the high halves from overwriting low halves still being read.
+// Each thread writes exactly the indices it read in the previous exchange, so
+// no barrier is needed before the first store of the next exchange.
+template <int LOGN, int B0, int LO0, int B1, int LO1>
+__device__ __forceinline__ void lds_exchange(uint64_t (&v)[16], uint64_t* lds, int tid) {
+  uint32_t* w = reinterpret_cast<uint32_t*>(lds);
+  uint32_t* st = w + lds_pad(eidx<LOGN, B0, LO0>(tid, 0));
+  const uint32_t* ld = w + lds_pad(eidx<LOGN, B1, LO1>(tid, 0));
+  uint32_t lo[16];
 #pragma unroll
-  for (int a = 0; a < 16; ++a) base[lds_pad(eidx<LOGN, B, LO>(0, a))] = v[a];
-}
-
-template <int LOGN, int B, int LO>
-__device__ __forceinline__ void lds_load(uint64_t (&v)[16], const uint64_t* lds, int tid) {
-  const uint64_t* base = lds + lds_pad(eidx<LOGN, B, LO>(tid, 0));
+  for (int a = 0; a < 16; ++a) st[lds_pad(eidx<LOGN, B0, LO0>(0, a))] = (uint32_t)v[a];
+  __syncthreads();
 #pragma unroll
-  for (int a = 0; a < 16; ++a) v[a] = base[lds_pad(eidx<LOGN, B, LO>(0, a))];
+  for (int a = 0; a < 16; ++a) lo[a] = ld[lds_pad(eidx<LOGN, B1, LO1>(0, a))];
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 16; ++a) st[lds_pad(eidx<LOGN, B0, LO0>(0, a))] = (uint32_t)(v[a] >> 32);
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 16; ++a)
+    v[a] = lo[a] | ((uint64_t)ld[lds_pad(eidx<LOGN, B1, LO1>(0, a))] << 32);
 }
 
 template <int LOGN, int J>
@@ -177,13 +193,10 @@ __device__ __forceinline__ void fwd_from(uint64_t (&v)[16], uint64_t* lds, int t
   constexpr int LO = S::fwd_lo(J), B = S::fwd_b(J);
   fwd_pass<LOGN, B, LO>(v, tid, tw, q);
   if constexpr (J + 1 < S::P) {
-    // Within later passes a thread stores exactly the positions it loaded,
-    // so one barrier before the first store (guarding LDS still read by an
-    // earlier transform of the workgroup) and one per exchange suffice.
+    // the barrier before the first store guards LDS still read by an
+    // earlier transform of the workgroup
     if (J == 0) __syncthreads();
-    lds_store<LOGN, B, LO>(v, lds, tid);
-    __syncthreads();
-    lds_load<LOGN, S::fwd_b(J + 1), S::fwd_lo(J + 1)>(v, lds, tid);
+    lds_exchange<LOGN, B, LO, S::fwd_b(J + 1), S::fwd_lo(J + 1)>(v, lds, tid);
     fwd_from<LOGN, J + 1>(v, lds, tid, tw, q);
   }
 }
@@ -196,9 +209,7 @@ __device__ __forceinline__ void inv_from(uint64_t (&v)[16], uint64_t* lds, int t
   inv_pass<LOGN, B, LO>(v, tid, tw, P.q);
   if constexpr (J + 1 < S::P) {
     if (J == 0) __syncthreads();
-    lds_store<LOGN, B, LO>(v, lds, tid);
-    __syncthreads();
-    lds_load<LOGN, S::inv_b(J + 1), S::inv_lo(J + 1)>(v, lds, tid);
+    lds_exchange<LOGN, B, LO, S::inv_b(J + 1), S::inv_lo(J + 1)>(v, lds, tid);
     inv_from<LOGN, J + 1>(v, lds, tid, tw, P);
   }
 }

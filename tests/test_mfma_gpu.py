@@ -82,12 +82,18 @@ def _check_rows(stage, pb, ctx, sk, out, share, rows, n_coeffs=16):
 
 
 # (N, L, t_bits, n, d, Q, dtype): ragged against the 64-row and 16-row tiles,
-# the 32- and 16-chunk tiles and the 64-coordinate steps
+# the 32- and 16-chunk tiles and the 64-coordinate steps; the ring degrees
+# 64 .. 512 cover every form of the split transforms (the forward head ends
+# and the inverse tail starts at a narrow pass of 2, 3, 4 or 1 bits)
 CASES = [
     (4096, 2, 25, 2 * 4096 + 77, 7, 5, "u8"),
     (8192, 3, 26, 8192 + 5, 100, 3, "i8"),
     (2048, 1, 20, 3 * 2048 + 1, 8, 9, "u8"),
     (16384, 3, 26, 16384 + 100, 128, 2, "i8"),
+    (64, 2, 22, 64 * 9 + 5, 4, 5, "u8"),
+    (128, 2, 22, 128 * 5 + 3, 5, 7, "i8"),
+    (256, 1, 25, 256 * 40 + 1, 70, 3, "u8"),
+    (512, 2, 25, 512 * 3, 33, 4, "i8"),
 ]
 
 
