@@ -97,7 +97,7 @@ typedef struct sanns_ctx sanns_ctx;
  *   norms    [n_chunks][N] uint32: ||p||^2 of the point in each slot (0 for
  *            padding slots);
  *   digits   (contexts created with SANNS_FLAG_DIGIT_DB, d <= 128 only)
- *            [L][N][n_chunks][7 Dp + 16] int8, Dp = d rounded up to 64: the
+ *            [L][N][n_chunks][7 Dp + 16] int8, Dp = d rounded up to 32: the
  *            same residues x as seven signed base-256 digits x_a in
  *            [-128, 127] (x = sum_a x_a 256^a), digit rows of Dp bytes
  *            indexed by coordinate, zero past d, then 16 padding bytes;

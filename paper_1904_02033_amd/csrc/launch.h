@@ -82,11 +82,12 @@ hipError_t launch_persistent(int shape, const PersistArgs& A, const PrimeSet& ps
 constexpr int kMfmaSchedule = 81;  // schedule id of sanns_set_schedule
 constexpr int kMfmaMaxD = 128;     // largest d (two MFMA steps of 64 coordinates)
 bool mfma_supported(int logN, int d);
-int mfma_padded_d(int d);   // d rounded up to 64
+int mfma_padded_d(int d);   // d rounded up to 32: database digit rows, contraction
+int mfma_query_d(int d);    // d rounded up to 64: query digit rows
 int mfma_db_stride(int d);  // bytes per (limb, slot, chunk) of the database digits
 size_t mfma_db_bytes(int C, int d, int L, int logN);  // the digit region, with its slack
 // Query NTT form grouped by 32 slots ([L][2Q][N/32][d][32] uint64, NTT output
-// form 2) -> query digits [L][N][2Q][7][Dp].
+// form 2) -> query digits [L][N][2Q][7][Dq], Dq = mfma_query_d(d).
 hipError_t launch_query_digits(const uint64_t* qntt, int8_t* qd, int Q, int d, int L, int logN,
                                hipStream_t st);
 // Database residues [L][C][d][N] (halves) -> database digits [L][N][C][Sk].

@@ -16,16 +16,21 @@
 // [0, q_l) with 64-bit integer steps and Shoup products.  Nothing here is
 // approximate: the result equals the one of the 64-bit vector kernels.
 //
-// Layouts (Dp = d rounded up to a multiple of 64, the coordinates of one MFMA
-// step being 64s .. 64s + 63; coordinate i >= d holds the digit 0):
-//   query digits    [L][N][R][7][Dp] int8    R = 2Q rows, row = 2q + c
+// Layouts (Dp = d rounded up to a multiple of 32, Dq = d rounded up to a
+// multiple of 64; the contraction runs in steps of 64 coordinates and, when
+// Dp is an odd multiple of 32, a last step of 32; coordinate i >= d holds the
+// digit 0):
+//   query digits    [L][N][R][7][Dq] int8    R = 2Q rows, row = 2q + c (rows
+//                                            of whole 128-byte lines)
 //   database digits [L][N][C][Sk] int8       Sk = 7 Dp + 16: digit rows, then
 //                                            16 bytes of padding (LDS banks)
 //   slot-major sums [L][N][Rp][Cp] uint64 below 2^58, congruent mod q_l (R and
 //                   C padded to whole tiles of 64 rows and 64 chunks)
 // Fragment of one lane (row or column m = lane % 16, group g = lane / 16) at
-// step s: the 16 bytes of one digit row at coordinates 64s + 16g .. + 15.
+// step s: the 16 bytes of one digit row at coordinates 64s + 16g .. + 15, or
+// in a 32-coordinate step the 8 bytes at 64s + 8g .. + 7.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include "kernels.h"
 #include "launch.h"
 
@@ -182,6 +187,44 @@ __device__ __forceinline__ void lds_frags(uint32_t addr, v4i (&bf)[7]) {
       : "v"(addr), "n"(DP), "n"(2 * DP), "n"(3 * DP), "n"(4 * DP), "n"(5 * DP), "n"(6 * DP));
 }
 
+// The same for a 32-coordinate step: 8-byte fragments.
+template <int DP>
+__device__ __forceinline__ void lds_frags(uint32_t addr, int64_t (&bf)[7]) {
+  asm volatile(
+      "ds_read_b64 %0, %7\n\t"
+      "ds_read_b64 %1, %7 offset:%8\n\t"
+      "ds_read_b64 %2, %7 offset:%9\n\t"
+      "ds_read_b64 %3, %7 offset:%10\n\t"
+      "ds_read_b64 %4, %7 offset:%11\n\t"
+      "ds_read_b64 %5, %7 offset:%12\n\t"
+      "ds_read_b64 %6, %7 offset:%13\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(bf[0]), "=&v"(bf[1]), "=&v"(bf[2]), "=&v"(bf[3]), "=&v"(bf[4]), "=&v"(bf[5]),
+        "=&v"(bf[6])
+      : "v"(addr), "n"(DP), "n"(2 * DP), "n"(3 * DP), "n"(4 * DP), "n"(5 * DP), "n"(6 * DP));
+}
+
+// One MFMA step of the contraction: 64 coordinates (16 bytes per lane,
+// v_mfma_i32_16x16x64_i8) or 32 (8 bytes per lane, v_mfma_i32_16x16x32_i8,
+// lane l supplying row or column l % 16 and contraction bytes 8 (l / 16) ..
+// + 7; the output layout is that of the 64-wide form).
+template <bool W32>
+struct StepFrag {
+  typedef v4i T;
+};
+template <>
+struct StepFrag<true> {
+  typedef int64_t T;
+};
+template <bool W32>
+__device__ __forceinline__ v4i mfma_digits(typename StepFrag<W32>::T a,
+                                           typename StepFrag<W32>::T b, v4i c) {
+  if constexpr (W32)
+    return __builtin_amdgcn_mfma_i32_16x16x32_i8(a, b, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+}
+
 // One workgroup: 64 rows x 64 chunks of kMfmaSlots consecutive slots of one
 // limb, the chunks taken as two halves of 32 that reuse the same query
 // fragments.  Wave w owns rows 16w .. 16w + 15 of the tile and the two
@@ -200,11 +243,17 @@ __device__ __forceinline__ void lds_frags(uint32_t addr, v4i (&bf)[7]) {
 // (and nothing newer); the stores go out after the barrier.  Workgroups are
 // numbered so that the tiles of one slot range run back to back on one XCD,
 // which shares the operands in its L2.
-template <int NKS>
+template <int DP>
 __global__ void __launch_bounds__(256, 2)
 k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R, int C, int L,
            int logN, int n_items, DigitSet ds, uint64_t* __restrict__ sums) {
-  constexpr int Dp = 64 * NKS, Sk = 7 * Dp + 16;
+  constexpr int Dp = DP, Sk = 7 * Dp + 16, Dq = (Dp + 63) / 64 * 64;
+  // steps of the contraction: one or two; step 0 is 32 coordinates wide when
+  // Dp = 32, step 1 when Dp = 96, every other step 64
+  constexpr int NS = (Dp + 63) / 64;
+  constexpr bool W0 = Dp < 64, W1 = Dp % 64 != 0;
+  typedef typename StepFrag<W0>::T F0;
+  typedef typename StepFrag<W1>::T F1;
   constexpr int H = kMfmaChunks / 2;        // chunks per half
   constexpr int BU = H * Sk / 16;           // 16-byte units of one staged half
   constexpr int BR = (BU + 255) / 256;      // DMA rounds of the 256 threads
@@ -237,12 +286,13 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
           (const void*)(src + tid + 256 * m),
           (__attribute__((address_space(3))) void*)(buf + 256 * m + 64 * w), 16, 0, 0);
   };
-  // Query fragments of one 64-coordinate step of slot p.
-  auto load_a = [&](int p, int ks, v4i (&af)[7]) {
-    const int8_t* ab =
-        qd + (((size_t)l * N + p) * R + arow) * (size_t)(7 * Dp) + 16 * g + 64 * ks;
+  // Query fragments of step ks of slot p.
+  auto load_a = [&](int p, int ks, auto (&af)[7]) {
+    typedef typename std::remove_reference<decltype(af[0])>::type F;
+    const int8_t* ab = qd + (((size_t)l * N + p) * R + arow) * (size_t)(7 * Dq) +
+                       (int)sizeof(F) * g + 64 * ks;
 #pragma unroll
-    for (int a = 0; a < 7; ++a) af[a] = *reinterpret_cast<const v4i*>(ab + a * Dp);
+    for (int a = 0; a < 7; ++a) af[a] = *reinterpret_cast<const F*>(ab + a * Dq);
   };
   // 98 MFMAs of one step: every digit pair (a, b) of both column tiles into
   // diagonal a + b; the first product of a diagonal starts from a zero
@@ -251,18 +301,21 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
   // asm block with its own wait: the compiler, which cannot tell the two
   // staging buffers apart, would otherwise hold every LDS read until a DMA
   // into the other buffer has landed).
-  auto mfma_step = [&](const v4i (&af)[7], int ks, uint32_t bbase, v4i (&acc)[2][13]) {
+  // The lane's byte offset in a staged chunk row is sizeof(fragment) g.
+  auto mfma_step = [&](const auto (&af)[7], int ks, uint32_t buf, v4i (&acc)[2][13]) {
+    typedef typename std::remove_const<
+        typename std::remove_reference<decltype(af[0])>::type>::type F;
+    constexpr bool W = sizeof(F) == 8;
 #pragma unroll
     for (int cs = 0; cs < 2; ++cs) {
-      v4i bf[7];
-      lds_frags<Dp>(bbase + cs * 16 * Sk + 64 * ks, bf);
+      F bf[7];
+      lds_frags<Dp>(buf + m16 * Sk + (int)sizeof(F) * g + cs * 16 * Sk + 64 * ks, bf);
 #pragma unroll
       for (int b = 0; b < 7; ++b)
 #pragma unroll
         for (int a = 0; a < 7; ++a)
-          acc[cs][a + b] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-              af[a], bf[b],
-              (ks == 0 && (b == 0 || a == 6)) ? v4i{0, 0, 0, 0} : acc[cs][a + b], 0, 0, 0);
+          acc[cs][a + b] = mfma_digits<W>(
+              af[a], bf[b], (ks == 0 && (b == 0 || a == 6)) ? v4i{0, 0, 0, 0} : acc[cs][a + b]);
     }
   };
   // Fold of the accumulators of one half into sums below 2^58.
@@ -287,12 +340,13 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
       for (int e = 0; e < 4; ++e) dst[(size_t)e * Cp + 16 * cs] = v[cs][e];
   };
 
-  const uint32_t b0 = lds_address(sb0) + m16 * Sk + 16 * g;
-  const uint32_t b1 = lds_address(sb1) + m16 * Sk + 16 * g;
-  v4i a0[7], a1[7];
+  const uint32_t b0 = lds_address(sb0);
+  const uint32_t b1 = lds_address(sb1);
+  F0 a0[7];
+  F1 a1[7];
   stage(p0, 0, sb0);
   load_a(p0, 0, a0);
-  if (NKS == 2) load_a(p0, 1, a1);
+  if (NS == 2) load_a(p0, 1, a1);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   for (int jj = 0; jj < kMfmaSlots; ++jj) {
@@ -308,7 +362,7 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
       __builtin_amdgcn_sched_barrier(0);
       v4i acc[2][13];
       mfma_step(a0, 0, b0, acc);
-      if (NKS == 2) mfma_step(a1, 1, b0, acc);
+      if constexpr (NS == 2) mfma_step(a1, 1, b0, acc);
       __builtin_amdgcn_sched_barrier(0);
       fold(acc, v);
       __builtin_amdgcn_sched_barrier(0);
@@ -323,7 +377,7 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
       v4i acc[2][13];
       mfma_step(a0, 0, b1, acc);
       __builtin_amdgcn_sched_barrier(0);
-      if (NKS == 2) {
+      if constexpr (NS == 2) {
         load_a(pn, 0, a0);  // step 0 of the next slot, during this step 1
         __builtin_amdgcn_sched_barrier(0);
         mfma_step(a1, 1, b1, acc);
@@ -336,7 +390,7 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
       fold(acc, v);
       __builtin_amdgcn_sched_barrier(0);
       // the DMA into sb0 (older than the newest 7 fragment loads per step)
-      __builtin_amdgcn_s_waitcnt(NKS == 2 ? kWaitAllBut14Vmem : kWaitAllBut7Vmem);
+      __builtin_amdgcn_s_waitcnt(NS == 2 ? kWaitAllBut14Vmem : kWaitAllBut7Vmem);
       __builtin_amdgcn_sched_barrier(0);
       __builtin_amdgcn_s_barrier();
       store(p, 1, v);
@@ -385,7 +439,8 @@ k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R
 // launchers
 // --------------------------------------------------------------------------
 
-int mfma_padded_d(int d) { return (d + 63) / 64 * 64; }
+int mfma_padded_d(int d) { return (d + 31) / 32 * 32; }
+int mfma_query_d(int d) { return (d + 63) / 64 * 64; }
 size_t mfma_sums_bytes(int Q, int C, int L, int logN) {
   const size_t Rp = (2 * (size_t)Q + kMfmaRows - 1) / kMfmaRows * kMfmaRows;
   const size_t Cp = ((size_t)C + kMfmaChunks - 1) / kMfmaChunks * kMfmaChunks;
@@ -402,7 +457,7 @@ bool mfma_supported(int logN, int d) {
 
 hipError_t launch_query_digits(const uint64_t* qntt, int8_t* qd, int Q, int d, int L, int logN,
                                hipStream_t st) {
-  const int Dp = mfma_padded_d(d), N = 1 << logN;
+  const int Dp = mfma_query_d(d), N = 1 << logN;
   const long nb = (long)L * 2 * Q * (N / kDigitSlots);
   if (nb <= 0) return hipSuccess;
   const size_t lds = (size_t)Dp * (kDigitSlots + 1) * sizeof(uint64_t);
@@ -422,14 +477,14 @@ hipError_t launch_db_digits(const uint2* dbres, int8_t* dbd, int C, int d, int L
   return hipGetLastError();
 }
 
-template <int NKS>
+template <int DP>
 static void launch_mac_mfma_t(const int8_t* qd, const int8_t* dbd, int R, int C, int L, int logN,
                               const DigitSet& ds, uint64_t* sums, hipStream_t st) {
   const int N = 1 << logN;
   const long n_items = (long)L * (N / kMfmaSlots) * ((R + kMfmaRows - 1) / kMfmaRows) *
                        ((C + kMfmaChunks - 1) / kMfmaChunks);
   const long per_xcd = (n_items + 7) >> 3;
-  hipLaunchKernelGGL(k_mac_mfma<NKS>, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, st, qd, dbd,
+  hipLaunchKernelGGL(k_mac_mfma<DP>, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, st, qd, dbd,
                      R, C, L, logN, (int)n_items, ds, sums);
 }
 
@@ -438,9 +493,11 @@ hipError_t launch_mac_mfma(const int8_t* qd, const int8_t* dbd, int Q, int d, in
   if (!mfma_supported(logN, d)) return hipErrorInvalidValue;
   if (Q <= 0 || C <= 0) return hipSuccess;
   const int R = 2 * Q;
-  switch (mfma_padded_d(d) / 64) {
-    case 1: launch_mac_mfma_t<1>(qd, dbd, R, C, L, logN, ds, sums, st); break;
-    case 2: launch_mac_mfma_t<2>(qd, dbd, R, C, L, logN, ds, sums, st); break;
+  switch (mfma_padded_d(d)) {
+    case 32: launch_mac_mfma_t<32>(qd, dbd, R, C, L, logN, ds, sums, st); break;
+    case 64: launch_mac_mfma_t<64>(qd, dbd, R, C, L, logN, ds, sums, st); break;
+    case 96: launch_mac_mfma_t<96>(qd, dbd, R, C, L, logN, ds, sums, st); break;
+    case 128: launch_mac_mfma_t<128>(qd, dbd, R, C, L, logN, ds, sums, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -140,13 +140,13 @@ bool db_has_digits(const sanns_ctx* ctx, uint32_t d) {
 // queries against C chunks of dimension d.  Relative costs per (limb, slot),
 // from the kernels' times at Q = 64, C = 123, d = 128: the 64-bit vector
 // multiply-accumulate 8.6 ms (scales with Q C d); the matrix-core path's
-// digit transpose 1.35 ms (Q Dp), MFMA tiles 2.4 ms (64-row x 64-chunk tiles
+// digit transpose 1.35 ms (Q Dq), MFMA tiles 2.4 ms (64-row x 64-chunk tiles
 // x Dp, 4 of them) and sums transpose 1.25 ms (Q C).
 bool mfma_expected_faster(uint32_t Q, uint32_t C, uint32_t d) {
-  const double Dp = mfma_padded_d((int)d);
+  const double Dp = mfma_padded_d((int)d), Dq = mfma_query_d((int)d);
   const double valu = 8.6 * (double)Q * C * d / (64.0 * 123 * 128);
   const double tiles = (double)((2 * Q + 63) / 64) * ((C + 63) / 64);
-  const double mfma = 1.35 * Q * Dp / (64.0 * 128) + 2.4 * tiles * Dp / (4.0 * 128) +
+  const double mfma = 1.35 * Q * Dq / (64.0 * 128) + 2.4 * tiles * Dp / (4.0 * 128) +
                       1.25 * (double)Q * C / (64.0 * 123);
   return mfma < valu;
 }
@@ -272,7 +272,7 @@ WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M, boo
   w.qdig = w.sums = off;
   if (mfma) {
     // matrix-core schedule: query digits and slot-major sums (all pairs: C = M / Q)
-    off += align256(L * N * 2 * Q * 7 * (size_t)mfma_padded_d((int)d));
+    off += align256(L * N * 2 * Q * 7 * (size_t)mfma_query_d((int)d));
     w.sums = off;
     off += align256(mfma_sums_bytes((int)Q, (int)((M + Q - 1) / Q), (int)L, ctx->logN));
   }
