@@ -69,6 +69,7 @@ def recorded_traffic(kernel: str):
 
 
 USE_DIGITS = True
+T_POW2 = False  # --t-pow2: plain modulus 2^(t_bits - 1) instead of the prime
 
 
 def digit_context(w):
@@ -79,6 +80,8 @@ def digit_context(w):
     params = nat.sanns_params_derive(w.N, w.L, w.t_bits)
     if USE_DIGITS:
         params.flags |= nat.SANNS_FLAG_DIGIT_DB
+    if T_POW2:
+        params.t = 1 << (w.t_bits - 1)
     return stage.Context(params=params)
 
 
@@ -127,12 +130,16 @@ def main():
                          "(used for profiler runs)")
     ap.add_argument("--no-digits", action="store_true",
                     help="create contexts without SANNS_FLAG_DIGIT_DB (vector schedules only)")
+    ap.add_argument("--t-pow2", action="store_true",
+                    help="plain modulus t = 2^(t_bits - 1), a power of two as in the paper's "
+                         "parameters, instead of the prime t = 1 mod 2N")
     ap.add_argument("--schedule", default="",
                     help="with --no-tune: run this schedule instead of the default "
                          "(mfma, lds<id>, persistent/<id>)")
     args = ap.parse_args()
-    global USE_DIGITS
+    global USE_DIGITS, T_POW2
     USE_DIGITS = not args.no_digits
+    T_POW2 = args.t_pow2
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the stage shards by database chunk; see the design notes)", flush=True)

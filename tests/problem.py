@@ -43,8 +43,11 @@ class Problem:
 
 def make_problem(N: int, L: int, t_bits: int, n: int, d: int, Q: int, dtype: str = "u8",
                  seed: int = 0, points: Optional[np.ndarray] = None,
-                 queries: Optional[np.ndarray] = None) -> Problem:
-    P = oracle.Params(N, oracle.rns_primes(N, L), oracle.plain_modulus(N, t_bits))
+                 queries: Optional[np.ndarray] = None, t: Optional[int] = None) -> Problem:
+    """t: the plain modulus (default: the prime of t_bits bits that the
+    workloads use)."""
+    P = oracle.Params(N, oracle.rns_primes(N, L),
+                      t if t is not None else oracle.plain_modulus(N, t_bits))
     g = np.random.default_rng(seed)
     if points is None:
         if dtype == "u8":

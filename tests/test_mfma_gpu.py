@@ -109,6 +109,21 @@ def test_mfma_matches_oracle_and_vector_schedule(stage, case):
     assert (vo == out).all() and (vs == share).all()
 
 
+@pytest.mark.parametrize("dt", ["u8", "i8"])
+def test_power_of_two_t(stage, dt):
+    """t = 2^24 (the paper's kind of plain modulus, Section 5): both
+    schedules agree with the oracle and with each other, and the shares
+    reconstruct every distance."""
+    from paper_1904_02033_amd import native as nat
+    pb = make_problem(4096, 2, 25, 2 * 4096 + 33, 100, 4, dt, seed=41, t=1 << 24)
+    ctx, db, sk, ct, qids = _setup(stage, pb)
+    assert ctx.t == 1 << 24
+    out, share = _run(stage, ctx, db, pb, ct, qids, nat.SANNS_MODE_BATCHED, MFMA)
+    _check_rows(stage, pb, ctx, sk, out, share, range(pb.Q * pb.C), n_coeffs=8)
+    vo, vs = _run(stage, ctx, db, pb, ct, qids, nat.SANNS_MODE_FUSED, 22)
+    assert (vo == out).all() and (vs == share).all()
+
+
 def test_mfma_many_tiles_equals_vector_schedule(stage):
     """66 rows (two row tiles, the second with 2 rows) x 33 chunks (two chunk
     tiles, the second with one chunk), d = 128: every output equal to the

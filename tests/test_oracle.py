@@ -204,10 +204,12 @@ def _toy_params(N=16, L=2, t=257):
     return oracle.Params(N, oracle.rns_primes(N, L), t)
 
 
-def test_decrypt_of_encrypt_exhaustive_small():
+@pytest.mark.parametrize("t", [257, 256])
+def test_decrypt_of_encrypt_exhaustive_small(t):
     """Dec(Enc(m)) = m for every m in Z_t, and a fresh ciphertext's noise is
-    exactly its error polynomial (c0 + c1 s = e + Delta m)."""
-    P = _toy_params()
+    exactly its error polynomial (c0 + c1 s = e + Delta m); for a prime t and
+    for t a power of two (the paper's choice, Section 5)."""
+    P = _toy_params(t=t)
     s = synthdata.gen_secret(P.N, 1)
     msgs = list(range(P.t))
     a = synthdata.gen_uniform_a(P.qs, P.N, len(msgs), 2)
@@ -246,8 +248,9 @@ def test_encoding_identity_plaintext():
     assert acc == [int(pts[j] @ qv) % t for j in range(N)]
 
 
-def _small_stage(n=40, d=6, N=16, L=2, t_bits=20, seed=0, dtype="u8"):
-    P = oracle.Params(N, oracle.rns_primes(N, L), oracle.plain_modulus(N, t_bits))
+def _small_stage(n=40, d=6, N=16, L=2, t_bits=20, seed=0, dtype="u8", t=None):
+    P = oracle.Params(N, oracle.rns_primes(N, L),
+                      t if t is not None else oracle.plain_modulus(N, t_bits))
     g = np.random.default_rng(seed)
     if dtype == "u8":
         pts = g.integers(0, 256, (n, d)).astype(np.uint8)
@@ -265,14 +268,18 @@ def _small_stage(n=40, d=6, N=16, L=2, t_bits=20, seed=0, dtype="u8"):
     return P, pts, qv, s, ct, slot, key
 
 
-@pytest.mark.parametrize("dtype", ["u8", "i8"])
-def test_share_sum_is_squared_distance(dtype):
+@pytest.mark.parametrize("dtype,t", [("u8", None), ("i8", None), ("u8", 1 << 20),
+                                     ("i8", 1 << 19)])
+def test_share_sum_is_squared_distance(dtype, t):
     """[client + server]_t = ||q - p||^2 for every real slot (closed form),
+    with t the prime of the workloads or a power of two (the paper's choice,
+    Section 5: the packing never needs slots of Z_t[x], so any t above the
+    largest distance works),
     padding slots decrypt to their mask only, and the noise obeys the bound
     d N eta max|g| + (q mod t)(d max|g| + 2): the product's integer message
     W = sum_i [q_i]_t g_i + [P - r]_t is W = M + tK with |K| <= d max|g| + 2,
     and Delta t K = -(q mod t) K mod q."""
-    P, pts, qv, s, ct, slot, key = _small_stage(dtype=dtype)
+    P, pts, qv, s, ct, slot, key = _small_stage(dtype=dtype, t=t)
     n, d = pts.shape
     C = len(slot) // P.N
     qn2 = int((qv.astype(np.int64) ** 2).sum()) % P.t
