@@ -42,8 +42,8 @@ constexpr uint64_t kDigitBias = 0x0080808080808080ull;  // 128 in each of bytes 
 constexpr int kMfmaRows = 64;    // rows per workgroup: 4 waves x 16
 constexpr int kMfmaChunks = 64;  // chunks per workgroup: 2 halves of 2 MFMA column tiles
 constexpr int kMfmaSlots = 8;    // consecutive slots per workgroup
-constexpr int kDigitSlots = 32;  // slots per workgroup of the digit transposes
-constexpr int kDigitThreads = 512;
+constexpr int kDigitGroup = 32;  // slots per group of the query NTT form (form 2)
+constexpr int kQueryDigitSlots = 16;  // slots per workgroup of the query digit transpose
 // The database digit region ends with this many spare bytes: a staged half
 // tile may run past the last chunk (at most 32 chunks of at most 7 x 128 + 16
 // bytes each, plus one DMA round of 256 x 16 bytes).
@@ -69,31 +69,31 @@ __device__ __forceinline__ uint32_t gather_byte(uint64_t y0, uint64_t y1, uint64
          (uint32_t)(((y2 >> sh) & 0xff) << 16) | (uint32_t)(((y3 >> sh) & 0xff) << 24);
 }
 
-// Transpose-and-digitise: a workgroup takes kDigitSlots consecutive slots of
-// one (limb, entity) pair, where the entity is a query row (source: the
-// query NTT form grouped by 32 slots, [L][R][N/32][d][32] uint64, so the
-// workgroup's d x 32 words are one contiguous block) or a database chunk
-// (source: the database residues [L][C][d][N] as 27-bit halves), stages the
-// words in LDS, and writes each slot's 7 digit rows of Dp bytes (16 bytes per
-// store, zero digits past coordinate d; two threads share a slot's
-// 16-coordinate group, one for digits 0-3, one for 4-6).  The query side is
-// read and written with nontemporal hints: it is touched once.
-template <bool DB>
-__global__ void __launch_bounds__(kDigitThreads)
+// Transpose-and-digitise: a workgroup of 16 S threads takes S consecutive
+// slots of one (limb, entity) pair, where the entity is a query row (source:
+// the query NTT form grouped by 32 slots, [L][R][N/32][d][32] uint64, so the
+// workgroup's d x S words are d runs of S in one contiguous block) or a
+// database chunk (source: the database residues [L][C][d][N] as 27-bit
+// halves), stages the words in LDS, and writes each slot's 7 digit rows of
+// Dp bytes (16 bytes per store, zero digits past coordinate d; two threads
+// share a slot's 16-coordinate group, one for digits 0-3, one for 4-6).  The
+// query side is read and written with nontemporal hints: it is touched once.
+template <bool DB, int S>
+__global__ void __launch_bounds__(16 * S)
 k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, int d, int Dp,
             int L, int logN, int C, int Sk) {
-  extern __shared__ uint64_t lw[];  // [Dp][kDigitSlots + 1]
-  constexpr int P1 = kDigitSlots + 1;
+  extern __shared__ uint64_t lw[];  // [Dp][S + 1]
+  constexpr int P1 = S + 1, NT = 16 * S;
   const int N = 1 << logN;
-  const int groups = N / kDigitSlots;
+  const int groups = N / S;
   int b = blockIdx.x;
   const int pg = b % groups;
   b /= groups;
   const int ent = b % n_ent, l = b / n_ent;
-  const int p0 = pg * kDigitSlots;
+  const int p0 = pg * S;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < Dp * kDigitSlots; idx += kDigitThreads) {
-    const int i = idx / kDigitSlots, pp = idx % kDigitSlots;
+  for (int idx = tid; idx < Dp * S; idx += NT) {
+    const int i = idx / S, pp = idx % S;
     uint64_t x = 0;
     if (i < d) {
       if (DB) {
@@ -101,8 +101,12 @@ k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, i
             src)[(((size_t)l * C + ent) * d + i) * N + p0 + pp];
         x = (uint64_t)h.x + ((uint64_t)h.y << 27);
       } else {
-        x = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(
-            src) + (((size_t)l * n_ent + ent) * groups + pg) * d * kDigitSlots + idx);
+        const int pq = p0 + pp;
+        x = __builtin_nontemporal_load(
+            reinterpret_cast<const uint64_t*>(src) +
+            ((((size_t)l * n_ent + ent) * (N / kDigitGroup) + pq / kDigitGroup) * d + i) *
+                kDigitGroup +
+            pq % kDigitGroup);
       }
     }
     lw[i * P1 + pp] = digit_word(x);
@@ -110,7 +114,7 @@ k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, i
   __syncthreads();
   const int cg_n = Dp / 16;
   typedef unsigned v4u __attribute__((ext_vector_type(4)));
-  for (int u = tid; u < 2 * kDigitSlots * cg_n; u += kDigitThreads) {
+  for (int u = tid; u < 2 * S * cg_n; u += NT) {
     const int hf = u & 1, cg = (u >> 1) % cg_n, pp = (u >> 1) / cg_n;
     const int p = p0 + pp;
     uint64_t y[16];
@@ -458,10 +462,11 @@ bool mfma_supported(int logN, int d) {
 hipError_t launch_query_digits(const uint64_t* qntt, int8_t* qd, int Q, int d, int L, int logN,
                                hipStream_t st) {
   const int Dp = mfma_query_d(d), N = 1 << logN;
-  const long nb = (long)L * 2 * Q * (N / kDigitSlots);
+  constexpr int S = kQueryDigitSlots;
+  const long nb = (long)L * 2 * Q * (N / S);
   if (nb <= 0) return hipSuccess;
-  const size_t lds = (size_t)Dp * (kDigitSlots + 1) * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_to_digits<false>, dim3((unsigned)nb), dim3(kDigitThreads), lds, st,
+  const size_t lds = (size_t)Dp * (S + 1) * sizeof(uint64_t);
+  hipLaunchKernelGGL((k_to_digits<false, S>), dim3((unsigned)nb), dim3(16 * S), lds, st,
                      (const void*)qntt, qd, 2 * Q, d, Dp, L, logN, 0, 0);
   return hipGetLastError();
 }
@@ -469,10 +474,10 @@ hipError_t launch_query_digits(const uint64_t* qntt, int8_t* qd, int Q, int d, i
 hipError_t launch_db_digits(const uint2* dbres, int8_t* dbd, int C, int d, int L, int logN,
                             hipStream_t st) {
   const int Dp = mfma_padded_d(d), N = 1 << logN;
-  const long nb = (long)L * C * (N / kDigitSlots);
+  const long nb = (long)L * C * (N / 32);
   if (nb <= 0) return hipSuccess;
-  const size_t lds = (size_t)Dp * (kDigitSlots + 1) * sizeof(uint64_t);
-  hipLaunchKernelGGL(k_to_digits<true>, dim3((unsigned)nb), dim3(kDigitThreads), lds, st,
+  const size_t lds = (size_t)Dp * (32 + 1) * sizeof(uint64_t);
+  hipLaunchKernelGGL((k_to_digits<true, 32>), dim3((unsigned)nb), dim3(512), lds, st,
                      (const void*)dbres, dbd, C, d, Dp, L, logN, C, mfma_db_stride(d));
   return hipGetLastError();
 }
