@@ -90,8 +90,9 @@ __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
 // 6 and 8 at which the compiler fits them in registers without spilling
 // (checked for every log2 N).  The forward needs 64-72 registers; at eight
 // waves (64 registers) the digit form fits except for log2 N = 8, 9 and 14,
-// the other forms do not.  The inverse with the mask needs 110-128 registers
-// at four waves and 75-80 at six, spilling at six for log2 N = 11, 12, 14.
+// the other forms do not.  The inverse with the mask takes up to 128
+// registers at four waves and 75-80 at six, where it spills for log2 N = 9,
+// 11, 12 and 14 (9 spills at four waves too, so it keeps six).
 constexpr int ntt_fwd_waves(int logn, int split) {
   return split == 2 && logn != 8 && logn != 9 && logn != 14 ? 8 : 6;
 }
