@@ -43,11 +43,16 @@ HBM_PEAK_GBS = 8000.0
 
 
 def device_source_hash() -> str:
+    """Hash of the device sources without their // comments and blank space,
+    so that the recorded counters stay valid across comment edits and go
+    stale on any change of code."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ["kernels.hip", "mfma.hip", "kernels.h", "modarith.h", "ntt.h"]:
-        with open(os.path.join(ROOT, "paper_1904_02033_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1904_02033_amd", "csrc", f)) as fh:
+            text = re.sub(r"//[^\n]*", "", fh.read())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
