@@ -40,7 +40,7 @@ def _dev(x, dtype=None):
     return t.cuda()
 
 
-class GpuRun:
+class DeviceRun:
     def __init__(self, stage, pb, work=None, mode=1, schedule=None, lds=0):
         self.ctx = _ctx(stage, pb)
         if schedule or lds:
@@ -133,7 +133,7 @@ SMALL = [
 def test_distances_small_full(stage, case, mode):
     N, L, tb, n, d, Q, dt = case
     pb = make_problem(N, L, tb, n, d, Q, dt, seed=sum(case[:6]) + mode)
-    run = GpuRun(stage, pb, mode=mode)
+    run = DeviceRun(stage, pb, mode=mode)
     out, share, client = run.np()
     work = _all_work(pb)
     want_out, want_r = oracle_outputs(pb, work, {})
@@ -154,7 +154,7 @@ def test_distances_uneven_work_list(stage, mode, schedule):
         work += [(qi, int(k)) for k in ks]
     order = g.permutation(len(work))
     work = [work[i] for i in order]
-    run = GpuRun(stage, pb, work=np.array(work, dtype=np.uint32), mode=mode,
+    run = DeviceRun(stage, pb, work=np.array(work, dtype=np.uint32), mode=mode,
                  schedule=schedule)
     out, share, client = run.np()
     want_out, want_r = oracle_outputs(pb, work, {})
@@ -171,7 +171,7 @@ def test_lds_mac_variants(stage, lds, mode, shape):
     leave ragged tiles, and with d > 255 (two accumulation folds)."""
     N, L, tb, n, d, Q, dt = shape
     pb = make_problem(N, L, tb, n, d, Q, dt, seed=lds + 10 * mode + d)
-    run = GpuRun(stage, pb, mode=mode, lds=lds)
+    run = DeviceRun(stage, pb, mode=mode, lds=lds)
     out, share, client = run.np()
     work = _all_work(pb)
     want_out, want_r = oracle_outputs(pb, work, {})
@@ -186,7 +186,7 @@ def test_workload1_full(stage, mode):
     w = synthdata.WORKLOADS[1]
     from problem import workload_problem
     pb = workload_problem(w, 1)
-    run = GpuRun(stage, pb, mode=mode)
+    run = DeviceRun(stage, pb, mode=mode)
     out, share, client = run.np()
     work = _all_work(pb)
     want_out, want_r = oracle_outputs(pb, work, {})
@@ -204,7 +204,7 @@ def test_workload1_full(stage, mode):
 def test_batched_graph_replay_picks_up_new_inputs(stage):
     """Replays of the cached graph read the current buffer contents."""
     pb = make_problem(256, 2, 25, 900, 6, 3, "u8", seed=21)
-    run = GpuRun(stage, pb, mode=2)
+    run = DeviceRun(stage, pb, mode=2)
     out1, share1, _ = run.np()
     pb2 = make_problem(256, 2, 25, 900, 6, 3, "u8", seed=21)
     pb2.queries = pb2.queries[::-1].copy()
@@ -224,7 +224,7 @@ def test_batched_graph_replay_picks_up_new_inputs(stage):
 def test_input_residue_out_of_range_is_reported(stage):
     from paper_1904_02033_amd import native as nat
     pb = make_problem(64, 2, 20, 100, 3, 1, "u8", seed=5)
-    run = GpuRun(stage, pb, mode=1)
+    run = DeviceRun(stage, pb, mode=1)
     host = run.ct.cpu().numpy().copy()
     host.reshape(-1)[7] = np.uint64(pb.P.qs[0] + 5)  # limb 0 of query 0
     run.D.run(_dev(host), pb.key, run.qids)
