@@ -56,10 +56,10 @@ def device_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+def recorded_traffic(kernel: str, summary: str = "batched_1Mx128_q64_hbm_counters.md"):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
     summary, or None when the device source changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "batched_1Mx128_q64_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", summary)
     try:
         text = open(path).read()
     except OSError:
@@ -662,7 +662,10 @@ def run_fused(args, ctx, db, F, ct1, key, q1, n, d, L, C, N):
              "phases_ms": {k: round(v, 4) for k, v in fph.items()},
              "roofline": {"bound": "hbm", "kernel": "k_mac", "achieved": round(mac1_gbs, 1),
                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": round(mac1_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                          "frac": round(mac1_gbs / HBM_PEAK_GBS, 4),
+                          "traffic": recorded_traffic("k_mac",
+                                                      "fused_1Mx128_q1_hbm_counters.md"),
+                          "traffic_unit": "bytes/launch",
                           "avg_ms": round(fph["mac"], 4),
                           "algorithmic": f"{mac1_bytes} B (resident DB + query NTT "
                                          "read + NTT-form outputs written)"}}
