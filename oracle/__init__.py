@@ -289,14 +289,6 @@ def noise(P: Params, ct: np.ndarray, s: np.ndarray, msg: Sequence[int],
 # the server's distance stage
 # ---------------------------------------------------------------------------
 
-def slot_map_linear(n: int, N: int, perm: np.ndarray) -> np.ndarray:
-    """Slot s of chunk k holds point perm[kN + s]; padding slots hold -1."""
-    C = (n + N - 1) // N
-    m = np.full(C * N, -1, dtype=np.int64)
-    m[:n] = perm
-    return m
-
-
 def chunk_plaintexts(points: np.ndarray, slot_pt: np.ndarray, N: int,
                      k: int) -> Tuple[np.ndarray, np.ndarray]:
     """g_{i,k}[j] = -2 p[i] for the point in slot j of chunk k (0 for padding),

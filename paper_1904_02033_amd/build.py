@@ -1,9 +1,14 @@
-"""Build the HIP library libsanns.so in-tree for gfx950 with hipcc."""
+"""Build the HIP library libsanns.so in-tree for gfx950 with hipcc.
+
+Each source is compiled to an object file in its own hipcc process (in
+parallel), then the objects are linked into the shared library.
+"""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -12,7 +17,7 @@ SOURCES = ["kernels.hip", "mfma.hip", "sanns_api.hip", "params.cpp"]
 ARCH = os.environ.get("SANNS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     # keep the compiler from forming packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
@@ -21,11 +26,23 @@ FLAGS = [
 
 def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
+    with tempfile.TemporaryDirectory(prefix="sanns_build_") as tmpdir:
+        objs, procs = [], []
+        for s in SOURCES:
+            obj = os.path.join(tmpdir, os.path.splitext(s)[0] + ".o")
+            cmd = [hipcc] + FLAGS + ["-c", os.path.join(CSRC, s), "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((s, subprocess.Popen(cmd)))
+            objs.append(obj)
+        failed = [s for s, p in procs if p.wait() != 0]
+        if failed:
+            raise subprocess.CalledProcessError(1, "hipcc -c " + " ".join(failed))
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     return LIB
 

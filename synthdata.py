@@ -171,6 +171,16 @@ def gen_perm(n: int, seed: int) -> np.ndarray:
     return rng(seed).permutation(n).astype(np.int64)
 
 
+def gen_slot_map(n: int, N: int, seed: int) -> np.ndarray:
+    """The server's random placement of n points into ceil(n/N) chunks of N
+    slots: slot s of chunk k holds point perm[kN + s] (perm = gen_perm(n,
+    seed)); the padding slots of the last chunk hold -1.  int64 [C N]."""
+    C = (n + N - 1) // N
+    out = np.full(C * N, -1, dtype=np.int64)
+    out[:n] = gen_perm(n, seed)
+    return out
+
+
 def gen_mask_key(seed: int) -> bytes:
     """256-bit key of the server's mask stream."""
     return rng(seed).integers(0, 256, size=32, dtype=np.uint8).tobytes()

@@ -64,8 +64,7 @@ def make_problem(N: int, L: int, t_bits: int, n: int, d: int, Q: int, dtype: str
     sk = synthdata.gen_secret(N, seed + 3000)
     a = synthdata.gen_uniform_a(P.qs, N, Q * d, seed + 4000).reshape(Q, d, L, N)
     e = synthdata.gen_cbd_error(N, Q * d, seed + 4000).reshape(Q, d, N)
-    perm = synthdata.gen_perm(n, seed + 2000)
-    slot = oracle.slot_map_linear(n, N, perm)
+    slot = synthdata.gen_slot_map(n, N, seed + 2000)
     key = synthdata.gen_mask_key(seed + 5000)
     qids = (np.arange(Q, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)
             + np.uint64(seed))

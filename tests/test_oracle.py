@@ -138,6 +138,39 @@ def test_plain_modulus(N, bits, want):
         c += 1
 
 
+def _golden_caps():
+    caps = {}
+    for line in open(os.path.join(GOLD, "he_standard_128bit_ternary.txt")):
+        if line.strip() and not line.startswith("#"):
+            n, b = line.split()
+            caps[int(n)] = int(b)
+    return caps
+
+
+def test_security_check_matches_he_standard_caps():
+    """Params.security_ok accepts exactly the moduli within the standard's
+    128-bit caps: at every tabulated N a modulus of the cap's bit length
+    passes and one bit more fails; degrees outside the table fail."""
+    caps = _golden_caps()
+    assert sorted(caps) == [1024, 2048, 4096, 8192, 16384, 32768]
+    for N, b in caps.items():
+        at = oracle.Params(N, [(1 << (b - 1)) + 1], 3)
+        over = oracle.Params(N, [(1 << b) + 1], 3)
+        assert at.q.bit_length() == b and at.security_ok(), N
+        assert over.q.bit_length() == b + 1 and not over.security_ok(), N
+        # split over several limbs the same way
+        two = oracle.Params(N, [(1 << (b // 2)) + 1, (1 << (b - b // 2 - 1)) + 1], 3)
+        assert two.q.bit_length() == b and two.security_ok(), N
+    for N in (16, 512, 3000, 65536):
+        assert not oracle.Params(N, [(1 << 20) + 1], 3).security_ok(), N
+    # the paper's own parameter set (N = 2^13, 180-bit q) is within its cap;
+    # the same q at N = 4096 is not
+    q180 = [(1 << 59) + 1, (1 << 59) + 3, (1 << 61) + 1]
+    assert oracle.Params(8192, q180, 1 << 23).q.bit_length() == 180
+    assert oracle.Params(8192, q180, 1 << 23).security_ok()
+    assert not oracle.Params(4096, q180, 1 << 23).security_ok()
+
+
 def test_workload_params_secure_and_wide_enough():
     for w in [synthdata.WORKLOADS[c] for c in (1, 2, 3)]:
         P = oracle.Params.for_workload(w.N, w.L, w.t_bits)
@@ -262,8 +295,7 @@ def _small_stage(n=40, d=6, N=16, L=2, t_bits=20, seed=0, dtype="u8", t=None):
     a = synthdata.gen_uniform_a(P.qs, N, d, seed + 2)
     e = synthdata.gen_cbd_error(N, d, seed + 3)
     ct = oracle.encrypt_constants(P, s, a, e, [int(x) for x in qv])
-    perm = synthdata.gen_perm(n, seed + 4)
-    slot = oracle.slot_map_linear(n, N, perm)
+    slot = synthdata.gen_slot_map(n, N, seed + 4)
     key = synthdata.gen_mask_key(seed + 5)
     return P, pts, qv, s, ct, slot, key
 
