@@ -78,11 +78,38 @@ def lib():
         L.oracle_masks.argtypes = [ctypes.c_char_p, ctypes.c_uint64,
                                    ctypes.c_uint32, ctypes.c_uint64,
                                    ctypes.c_int, ctypes.c_int, u32p]
+        L.oracle_sample_ternary.argtypes = [ctypes.c_uint64, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_int8)]
+        L.oracle_sample_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32,
+                                            ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int,
+                                            u64p]
+        L.oracle_sample_cbd21.argtypes = [ctypes.c_uint64, ctypes.c_uint32,
+                                          ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int16)]
+        L.oracle_cp_streams.argtypes = [ctypes.c_char_p, ctypes.c_uint64, ctypes.c_uint32,
+                                        ctypes.c_int, ctypes.POINTER(ctypes.c_int8),
+                                        ctypes.POINTER(ctypes.c_int16),
+                                        ctypes.POINTER(ctypes.c_int16), u32p]
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_threads.restype = None
+        L.oracle_max_threads.argtypes = []
+        L.oracle_max_threads.restype = ctypes.c_int
         L.oracle_sqdist.argtypes = [ctypes.POINTER(ctypes.c_int32),
                                     ctypes.POINTER(ctypes.c_int32),
                                     ctypes.c_int64, ctypes.c_int, i64p]
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Run the OpenMP loops on n threads; returns the count now in effect."""
+    lib().oracle_set_threads(int(n))
+    return int(lib().oracle_max_threads())
+
+
+def max_threads() -> int:
+    return int(lib().oracle_max_threads())
 
 
 def _p(arr, ct):
@@ -239,6 +266,45 @@ def encrypt_constants(P: Params, s: np.ndarray, a: np.ndarray, e: np.ndarray,
     return ct
 
 
+def sample_secret(seed: int, N: int) -> np.ndarray:
+    """Ternary secret key drawn from a seed (ChaCha20 stream, purpose 1)."""
+    out = np.empty(N, dtype=np.int8)
+    lib().oracle_sample_ternary(seed, N, _p(out, ctypes.c_int8))
+    return out
+
+
+def sample_encryption(P: Params, seed: int, Q: int, d: int
+                      ) -> Tuple[np.ndarray, np.ndarray]:
+    """Uniform components a [Q][d][L][N] and errors e [Q][d][N] (CBD, eta =
+    21) of Q encrypted queries of d coordinates, drawn from a seed (ChaCha20
+    streams, purposes 2 and 3, nonce = (query, coordinate, limb))."""
+    return _sample_ae(P, seed, Q, d, 2, 3)
+
+
+def _sample_ae(P: Params, seed: int, Q: int, d: int, pa: int, pe: int):
+    N = P.N
+    a = np.empty((Q, d, P.L, N), dtype=np.uint64)
+    e = np.empty((Q, d, N), dtype=np.int16)
+    for qi in range(Q):
+        for i in range(d):
+            for l, ql in enumerate(P.qs):
+                row = np.empty(N, dtype=np.uint64)
+                lib().oracle_sample_uniform(seed, pa, qi, i, l, ql, N,
+                                            _p(row, ctypes.c_uint64))
+                a[qi, i, l] = row
+            row = np.empty(N, dtype=np.int16)
+            lib().oracle_sample_cbd21(seed, pe, qi, i, N, _p(row, ctypes.c_int16))
+            e[qi, i] = row
+    return a, e
+
+
+def sample_public_key(P: Params, s: np.ndarray, seed: int) -> np.ndarray:
+    """The client's public key [2][L][N] with its a and e drawn from a seed
+    (purposes 4 and 5, nonce (0, 0, limb) and (0, 0, 0))."""
+    a, e = _sample_ae(P, seed, 1, 1, 4, 5)
+    return public_key(P, s, a[0, 0], e[0, 0])
+
+
 def phase(P: Params, ct: np.ndarray, s: np.ndarray,
           coeffs: Sequence[int] = None) -> List[int]:
     """x = c0 + c1*s mod q as big integers (CRT over the limbs).
@@ -357,6 +423,63 @@ def client_shares(P: Params, ct_out: np.ndarray, s: np.ndarray, qnorm2: int,
     """Client share [Dec(f) + ||q||^2]_t for one output ciphertext."""
     m = decrypt(P, ct_out, s, coeffs)
     return np.array([(x + qnorm2) % P.t for x in m], dtype=np.uint32)
+
+
+# ---------------------------------------------------------------------------
+# circuit privacy: re-randomisation and noise flooding (Section 2.3: the AHE
+# must hide the server's computation, by noise flooding; Section 5
+# "Parameters": statistical circuit privacy)
+# ---------------------------------------------------------------------------
+
+def public_key(P: Params, s: np.ndarray, a: np.ndarray, e: np.ndarray) -> np.ndarray:
+    """The client's public key [2][L][N]: p1 = a, p0 = -a*s + e (mod q_l),
+    an encryption of zero.  a: [L][N] uniform residues, e: [N] small errors."""
+    return encrypt_constants(P, s, a[None], e[None], [0])[0]
+
+
+def flood_bits(P: Params) -> int:
+    """Default width b of the flooding noise, uniform in [-2^b, 2^b): the
+    largest b with 2^b <= Delta / 4, so that the flood takes at most a quarter
+    of the decryption margin Delta / 2."""
+    return P.delta.bit_length() - 3
+
+
+def cp_randomness(P: Params, key: bytes, query_id: int, chunk: int, b: int):
+    """u (ternary), e1, e2 (CBD, eta = 21) and the flood integers
+    X_j mod 2^(b+1) - 2^b of one output, from the server's key."""
+    N = P.N
+    u = np.empty(N, dtype=np.int8)
+    e1 = np.empty(N, dtype=np.int16)
+    e2 = np.empty(N, dtype=np.int16)
+    words = np.empty((N, 8), dtype=np.uint32)
+    lib().oracle_cp_streams(key, query_id, chunk, N, _p(u, ctypes.c_int8),
+                            _p(e1, ctypes.c_int16), _p(e2, ctypes.c_int16),
+                            _p(words, ctypes.c_uint32))
+    flood = []
+    for j in range(N):
+        X = 0
+        for w in reversed(words[j]):
+            X = (X << 32) | int(w)
+        flood.append((X % (1 << (b + 1))) - (1 << b))
+    return u, e1, e2, flood
+
+
+def rerandomize(P: Params, f: np.ndarray, pk: np.ndarray, key: bytes, query_id: int,
+                chunk: int, b: int) -> np.ndarray:
+    """f + (p0 u + e1 + flood, p1 u + e2) for one output ciphertext f
+    [2][L][N]: a fresh encryption of zero under the client's public key
+    (re-randomises both components) plus noise flooding in c0."""
+    u, e1, e2, flood = cp_randomness(P, key, query_id, chunk, b)
+    out = np.empty_like(f)
+    for l, ql in enumerate(P.qs):
+        pu0 = mul_small(pk[0, l], u, ql).astype(object)
+        pu1 = mul_small(pk[1, l], u, ql).astype(object)
+        c0 = [(int(f[0, l, j]) + int(pu0[j]) + int(e1[j]) + flood[j]) % ql
+              for j in range(P.N)]
+        c1 = [(int(f[1, l, j]) + int(pu1[j]) + int(e2[j])) % ql for j in range(P.N)]
+        out[0, l] = np.array(c0, dtype=np.uint64)
+        out[1, l] = np.array(c1, dtype=np.uint64)
+    return out
 
 
 # ---------------------------------------------------------------------------

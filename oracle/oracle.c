@@ -19,6 +19,12 @@
 #include <stdint.h>
 #include <stddef.h>
 #include <string.h>
+#include <omp.h>
+
+/* Threads of the OpenMP loops below (the benchmark times the oracle on one
+ * thread and on every core the process may use). */
+void oracle_set_threads(int n) { omp_set_num_threads(n); }
+int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 typedef unsigned __int128 u128;
 typedef __int128 i128;
@@ -144,6 +150,115 @@ void oracle_masks(const uint8_t key_bytes[32], uint64_t query_id,
         u128 X = (u128)w[0] | (u128)w[1] << 32 | (u128)w[2] << 64 |
                  (u128)w[3] << 96;
         out[n] = (uint32_t)(X % t);
+    }
+}
+
+/* The client's randomness when it is drawn from a seed (key generation and
+ * encryption; the private-key AHE of Section 2.3): ChaCha20 with
+ * key = (seed low word, seed high word, purpose, 0, 0, 0, 0, 0), purpose
+ * 1 = secret key, 2 = uniform component a, 3 = error e, 4 and 5 = the same
+ * for the public key. */
+static void client_key(uint64_t seed, uint32_t purpose, uint32_t key[8])
+{
+    memset(key, 0, 8 * sizeof key[0]);
+    key[0] = (uint32_t)seed;
+    key[1] = (uint32_t)(seed >> 32);
+    key[2] = purpose;
+}
+
+/* 64-bit word n (n in [0, 8)) of a block: words 2n (low) and 2n + 1. */
+static uint64_t word64(const uint32_t blk[16], int n)
+{
+    return (uint64_t)blk[2 * n] | (uint64_t)blk[2 * n + 1] << 32;
+}
+
+/* Ternary secret s_j = (x_j mod 3) - 1, x_j the 64-bit word j % 8 of block
+ * j / 8, nonce (0, 0, 0). */
+void oracle_sample_ternary(uint64_t seed, int N, int8_t *out)
+{
+    uint32_t key[8], nonce[3] = {0, 0, 0}, blk[16];
+    client_key(seed, 1, key);
+    for (int j = 0; j < N; j++) {
+        oracle_chacha20_block(key, (uint32_t)(j / 8), nonce, blk);
+        out[j] = (int8_t)((int)(word64(blk, j % 8) % 3) - 1);
+    }
+}
+
+/* Uniform residue a_j in [0, q) of (query qi, coordinate i, limb l): the
+ * 128-bit little-endian integer of words 4(j%4) .. 4(j%4)+3 of block j / 4,
+ * nonce (qi, i, l), reduced mod q.  Purpose 2 for encryptions, 4 for the
+ * public key. */
+void oracle_sample_uniform(uint64_t seed, uint32_t purpose, uint32_t qi, uint32_t i,
+                           uint32_t l, uint64_t q, int N, uint64_t *out)
+{
+    uint32_t key[8], nonce[3] = {qi, i, l}, blk[16];
+    client_key(seed, purpose, key);
+    for (int j = 0; j < N; j++) {
+        oracle_chacha20_block(key, (uint32_t)(j / 4), nonce, blk);
+        const uint32_t *w = blk + 4 * (j % 4);
+        u128 X = (u128)w[0] | (u128)w[1] << 32 | (u128)w[2] << 64 | (u128)w[3] << 96;
+        out[j] = (uint64_t)(X % q);
+    }
+}
+
+/* Centred binomial error with eta = 21 of (query qi, coordinate i):
+ * e_j = popcount(bits 0..20 of x_j) - popcount(bits 21..41 of x_j), x_j the
+ * 64-bit word j % 8 of block j / 8, nonce (qi, i, 0).  Purpose 3 for
+ * encryptions, 5 for the public key. */
+void oracle_sample_cbd21(uint64_t seed, uint32_t purpose, uint32_t qi, uint32_t i, int N,
+                         int16_t *out)
+{
+    uint32_t key[8], nonce[3] = {qi, i, 0}, blk[16];
+    client_key(seed, purpose, key);
+    for (int j = 0; j < N; j++) {
+        oracle_chacha20_block(key, (uint32_t)(j / 8), nonce, blk);
+        const uint64_t x = word64(blk, j % 8);
+        int pa = 0, pb = 0;
+        for (int b = 0; b < 21; b++) {
+            pa += (int)((x >> b) & 1);
+            pb += (int)((x >> (21 + b)) & 1);
+        }
+        out[j] = (int16_t)(pa - pb);
+    }
+}
+
+/* The server's re-randomisation and flooding randomness of one output (query
+ * id, chunk), for circuit privacy (Section 2.3; Section 5 "Parameters"):
+ * ChaCha20 under the server's mask key and the mask stream's nonce (query id
+ * low word, high word, chunk), with the block counter of stream s starting at
+ * s * 2^24 (s = 0 is the mask stream itself):
+ *   s = 1  u_j  = (x_j mod 3) - 1,
+ *   s = 2  e1_j = popcount(bits 0..20 of x_j) - popcount(bits 21..41 of x_j),
+ *   s = 3  e2_j likewise,
+ *   with x_j the 64-bit word (2n, 2n+1), n = j % 8, of block j / 8;
+ *   s = 4  the eight words 8(j%2) .. 8(j%2)+7 of block j / 2 (a 256-bit
+ *          little-endian integer; the caller keeps its low bits). */
+void oracle_cp_streams(const uint8_t key_bytes[32], uint64_t query_id,
+                       uint32_t chunk, int N, int8_t *u, int16_t *e1,
+                       int16_t *e2, uint32_t *flood_words)
+{
+    uint32_t key[8], nonce[3] = {(uint32_t)query_id, (uint32_t)(query_id >> 32),
+                                 chunk}, blk[16];
+    for (int i = 0; i < 8; i++)
+        key[i] = (uint32_t)key_bytes[4 * i] | (uint32_t)key_bytes[4 * i + 1] << 8 |
+                 (uint32_t)key_bytes[4 * i + 2] << 16 |
+                 (uint32_t)key_bytes[4 * i + 3] << 24;
+    for (int j = 0; j < N; j++) {
+        oracle_chacha20_block(key, (1u << 24) + (uint32_t)(j / 8), nonce, blk);
+        u[j] = (int8_t)((int)(word64(blk, j % 8) % 3) - 1);
+        for (int s = 0; s < 2; s++) {
+            oracle_chacha20_block(key, ((uint32_t)(2 + s) << 24) + (uint32_t)(j / 8),
+                                  nonce, blk);
+            const uint64_t x = word64(blk, j % 8);
+            int pa = 0, pb = 0;
+            for (int b = 0; b < 21; b++) {
+                pa += (int)((x >> b) & 1);
+                pb += (int)((x >> (21 + b)) & 1);
+            }
+            (s == 0 ? e1 : e2)[j] = (int16_t)(pa - pb);
+        }
+        oracle_chacha20_block(key, (4u << 24) + (uint32_t)(j / 2), nonce, blk);
+        memcpy(flood_words + 8 * (size_t)j, blk + 8 * (j % 2), 8 * sizeof(uint32_t));
     }
 }
 

@@ -471,3 +471,160 @@ def test_packing_matches_paper_communication():
         cts = d + -(-n // N)
         ours = cts * 2 * N * logq / 8 / 1e6
         assert abs(ours - mb) / mb < 0.10, name
+
+
+# ---------------------------------------------------------------- seeded client randomness
+
+def test_seeded_secret_is_uniform_ternary():
+    """(x mod 3) - 1 over 64-bit ChaCha20 words: each of -1, 0, 1 with
+    probability 1/3 (bias below 2^-62), so the counts of 2^16 draws lie
+    within 5 sigma of N/3; different seeds give different keys."""
+    N = 1 << 16
+    s = oracle.sample_secret(11, N)
+    assert s.dtype == np.int8 and set(np.unique(s)) == {-1, 0, 1}
+    sigma = math.sqrt(N * (1 / 3) * (2 / 3))
+    for v in (-1, 0, 1):
+        assert abs(int((s == v).sum()) - N / 3) < 5 * sigma, v
+    assert (oracle.sample_secret(11, N) == s).all()
+    assert (oracle.sample_secret(12, 4096) != s[:4096]).any()
+    # consecutive coefficients come from one block and are not equal in a run
+    assert (s[:-1] != s[1:]).mean() > 0.6
+
+
+def test_seeded_encryption_randomness_distributions():
+    """a uniform in [0, q_l) (128-bit integers mod q_l, bias below 2^-74):
+    mean within 5 sigma of q/2 and 16 equal bins pass a chi-square test at
+    the 0.1% level; e a centred binomial with eta = 21: |e| <= 21, mean 0
+    and variance eta/2 = 10.5 within 5 sigma."""
+    P = oracle.Params(4096, oracle.rns_primes(4096, 2), 65537)
+    a, e = oracle.sample_encryption(P, 21, 2, 8)
+    for l, q in enumerate(P.qs):
+        x = a[:, :, l, :].astype(np.float64).ravel() / q
+        assert (a[:, :, l, :] < q).all()
+        n = x.size
+        assert abs(x.mean() - 0.5) < 5 * math.sqrt(1 / (12 * n))
+        counts = np.bincount(np.minimum((x * 16).astype(int), 15), minlength=16)
+        chi2 = float(((counts - n / 16) ** 2 / (n / 16)).sum())
+        assert chi2 < 37.7, chi2  # 99.9% quantile, 15 degrees of freedom
+    v = e.astype(np.float64).ravel()
+    assert np.abs(e).max() <= 21
+    assert abs(v.mean()) < 5 * math.sqrt(10.5 / v.size)
+    # variance of the sample variance: (mu4 - sigma^4) / n, mu4 = 3 s^4 - s^2 / 2
+    s2 = 10.5
+    sd = math.sqrt((3 * s2 ** 2 - s2 / 2 - s2 ** 2) / v.size)
+    assert abs(v.var() - s2) < 5 * sd, v.var()
+    # streams differ by query, coordinate and limb
+    assert (a[0, 0, 0] != a[1, 0, 0]).any() and (a[0, 0, 0] != a[0, 1, 0]).any()
+    assert (e[0, 0] != e[0, 1]).any()
+
+
+def test_seeded_encryption_decrypts():
+    """Encryption with seeded (s, a, e) decrypts to the message and its noise
+    is exactly e (Section 2.3)."""
+    P = oracle.Params(64, oracle.rns_primes(64, 2), 257)
+    s = oracle.sample_secret(3, 64)
+    a, e = oracle.sample_encryption(P, 4, 1, 3)
+    msgs = [5, 256, 100]
+    ct = oracle.encrypt_constants(P, s, a[0], e[0], msgs)
+    for i, m in enumerate(msgs):
+        want = [m % P.t] + [0] * 63
+        assert oracle.decrypt(P, ct[i], s) == want
+        assert oracle.noise(P, ct[i], s, want) == [int(x) for x in e[0, i]]
+
+
+# ---------------------------------------------------------------- circuit privacy
+
+def _int_negacyclic(a, b):
+    """Integer (unreduced) negacyclic product of two small polynomials."""
+    N = len(a)
+    out = [0] * N
+    for u in range(N):
+        for v in range(N):
+            w = int(a[u]) * int(b[v])
+            if u + v < N:
+                out[u + v] += w
+            else:
+                out[u + v - N] -= w
+    return out
+
+
+def test_rerandomized_output_noise_decomposes_exactly():
+    """Re-randomisation adds exactly the noise of a fresh encryption of zero
+    plus the flood: noise(f') - noise(f) = e_pk u + e1 + e2 s + flood, term by
+    term (integer polynomial products computed independently here), and the
+    message is unchanged (client + server shares still equal the squared
+    distances)."""
+    P, pts, qv, s, ct, slot, key = _small_stage(n=30, d=5, N=16, L=2, t_bits=20)
+    b = oracle.flood_bits(P)
+    apk = synthdata.gen_uniform_a(P.qs, P.N, 1, 90)[0]
+    epk = synthdata.gen_cbd_error(P.N, 1, 90)[0]
+    pk = oracle.public_key(P, s, apk, epk)
+    qn2 = int((qv.astype(np.int64) ** 2).sum()) % P.t
+    dist = ((pts.astype(np.int64) - qv.astype(np.int64)) ** 2).sum(axis=1)
+    for k in range(len(slot) // P.N):
+        g, nrm = oracle.chunk_plaintexts(pts, slot, P.N, k)
+        f, r = oracle.server_chunk(P, ct, g, nrm, key, 41, k)
+        f2 = oracle.rerandomize(P, f, pk, key, 41, k, b)
+        assert (f2[1] != f[1]).any()
+        msg = oracle.decrypt(P, f, s)
+        assert oracle.decrypt(P, f2, s) == msg
+        u, e1, e2, flood = oracle.cp_randomness(P, key, 41, k, b)
+        eu = _int_negacyclic(epk, u)
+        e2s = _int_negacyclic(e2, s)
+        want = [eu[j] + int(e1[j]) + e2s[j] + flood[j] for j in range(P.N)]
+        got = [x - y for x, y in zip(oracle.noise(P, f2, s, msg), oracle.noise(P, f, s, msg))]
+        assert got == want
+        cs = oracle.client_shares(P, f2, s, qn2)
+        ids = slot[k * P.N:(k + 1) * P.N]
+        for j in range(P.N):
+            tot = (int(cs[j]) + int(r[j])) % P.t
+            assert tot == (dist[ids[j]] if ids[j] >= 0 else qn2)
+
+
+def test_flood_width_and_margin():
+    """The flood is uniform in [-2^b, 2^b) with 2^b <= Delta / 4; at the
+    workloads' parameters the remaining margin holds the product noise bound
+    d N eta max|g| + (q mod t)(d max|g| + 2) plus the re-randomisation noise
+    (2 N eta + eta) with room to spare; flooding two bits wider would exceed
+    the decryption margin Delta / 2 - t (a plausible off-by-two fails)."""
+    for w, maxp in ((synthdata.WORKLOADS[1], 255), (synthdata.WORKLOADS[2], 255),
+                    (synthdata.WORKLOADS[3], 127)):
+        P = oracle.Params.for_workload(w.N, w.L, w.t_bits)
+        b = oracle.flood_bits(P)
+        assert (1 << b) <= P.delta // 4 < (1 << (b + 1))
+        maxg = 2 * maxp
+        prod = w.d * P.N * 21 * maxg + (P.q % P.t) * (w.d * maxg + 2)
+        rr = 2 * P.N * 21 + 21
+        assert (1 << b) + prod + rr < P.delta // 2 - P.t
+        assert (1 << (b + 2)) > P.delta // 2
+        # statistical distance of flood + v from flood, per ciphertext (N
+        # coefficients): N (prod + rr) / 2^b; the bits it leaves
+        # bound on the statistical distance: about 2^-82 at the N = 8192,
+        # 162-bit workloads, only 2^-29 at the N = 4096, 108-bit one (the
+        # paper's 108 bits need its 180-bit q)
+        lam = b - math.log2(P.N * (prod + rr))
+        assert lam > (80 if w.N == 8192 else 25), (w.cid, lam)
+    P = oracle.Params(16, oracle.rns_primes(16, 2), 257)
+    b = oracle.flood_bits(P)
+    fl = []
+    for ch in range(64):
+        fl += oracle.cp_randomness(P, bytes(range(32)), 3, ch, b)[3]
+    assert min(fl) >= -(1 << b) and max(fl) < (1 << b)
+    x = np.array([f / (1 << b) for f in fl])
+    assert abs(x.mean()) < 5 * math.sqrt(1 / (3 * len(x)))
+    assert x.min() < -0.9 and x.max() > 0.9
+
+
+def test_flooding_too_wide_breaks_decryption():
+    """A flood of width 2^(b+3) (beyond the margin) decrypts wrongly somewhere:
+    the margin check above is not vacuous."""
+    P, pts, qv, s, ct, slot, key = _small_stage(n=16, d=3, N=16, L=2, t_bits=20)
+    b = oracle.flood_bits(P)
+    apk = synthdata.gen_uniform_a(P.qs, P.N, 1, 91)[0]
+    epk = synthdata.gen_cbd_error(P.N, 1, 91)[0]
+    pk = oracle.public_key(P, s, apk, epk)
+    g, nrm = oracle.chunk_plaintexts(pts, slot, P.N, 0)
+    f, r = oracle.server_chunk(P, ct, g, nrm, key, 5, 0)
+    bad = sum(oracle.decrypt(P, oracle.rerandomize(P, f, pk, key, 5, k, b + 3), s)
+              != oracle.decrypt(P, f, s) for k in range(4))
+    assert bad >= 1
