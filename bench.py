@@ -120,7 +120,7 @@ def main():
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-queries", type=int, default=1)
-    ap.add_argument("--forms", default="batched,fused,plain",
+    ap.add_argument("--forms", default="batched,private,fused,plain",
                     help="comma list of forms to run besides the batched headline")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
@@ -179,7 +179,7 @@ def run_linear(args, w):
     n, d = pts.shape
     ctx = digit_context(w)
     N, L, t = ctx.N, ctx.L, ctx.t
-    slot = stage.linear_slot_map(n, N, synthdata.gen_perm(n, synthdata.SEED_PERM + w.cid))
+    slot = synthdata.gen_slot_map(n, N, synthdata.SEED_PERM + w.cid)
     db = stage.encode_db(ctx, pts, slot)
     C = db.n_chunks
     sk = torch.as_tensor(synthdata.gen_secret(N, synthdata.SEED_SK + w.cid)).to(dev)
@@ -286,10 +286,20 @@ def run_linear(args, w):
     if w.cid == 2 and Q == 64:
         traffic = recorded_traffic(mac_kernel.split()[0])
     roofline.update({"traffic": traffic, "traffic_unit": "bytes/launch",
-                     "avg_ms": round(mac_ms, 4)})
+                     "avg_ms": round(mac_ms, 4),
+                     # the same launch in the method's own units
+                     "modular_mul_acc_per_s": round(mulacc / (mac_ms * 1e-3), 1),
+                     "distances_per_s_in_kernel": round(Q * n / (mac_ms * 1e-3), 1)})
     if traffic:
         roofline["hbm_gbs"] = round(traffic / (mac_ms * 1e-3) / 1e9, 1)
     log(f"phases (ms): {phases}")
+
+    # ------------------------------------- circuit-private form (same batch)
+    private = None
+    if "private" in forms and Q >= 1:
+        private = run_private(args, ctx, db, pbest, ct, key, qids, sk, queries, slot, pts,
+                              value, ms_per_step)
+        best.apply(ctx)
 
     if args.calib_copy_mib:
         src = torch.empty(args.calib_copy_mib << 20, dtype=torch.uint8, device=dev)
@@ -364,9 +374,56 @@ def run_linear(args, w):
                        "N": N},
         "roofline": roofline if Q > 1 or not fused else fused["roofline"],
         "cpu_baseline": cpu,
+        "private_form": private,
     }
     ctx.close()
     return line
+
+
+def run_private(args, ctx, db, sched, ct, key, qids, sk, queries, slot, pts, value,
+                ms_per_step):
+    """The same batch in the circuit-private form (re-randomisation under the
+    client's public key plus noise flooding): step time, distances/s and the
+    cost over the plain batched step; every query shares one client's key."""
+    import torch
+    from paper_1904_02033_amd import native as nat, stage
+    Q, N, t = ct.shape[0], ctx.N, ctx.t
+    sched.apply(ctx)
+    pk = stage.public_key(ctx, sk, 4321)
+    pks = pk[None].expand(Q, *pk.shape).contiguous()
+    D = stage.Distances(ctx, db, Q, mode=nat.SANNS_MODE_BATCHED, private=True)
+    for _ in range(args.warmup):
+        D.run(ct, key, qids, pk=pks)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        D.run(ct, key, qids, pk=pks)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ctx.device_status()
+    # the shares of query 0, chunk 0 still reconstruct the true distances
+    qn2 = np.array([int((queries[0].astype(np.int64) ** 2).sum()) % t], dtype=np.uint32)
+    client = stage.decrypt_shares(ctx, sk, D.ct_out[:1].contiguous(),
+                                  torch.as_tensor(qn2).to(ct.device))
+    tot = (client.cpu().numpy()[0].astype(np.int64) +
+           D.share[0].cpu().numpy().astype(np.int64)) % t
+    ids = slot[:N]
+    real = ids >= 0
+    want = ((pts[ids[real]].astype(np.int64) - queries[0].astype(np.int64)) ** 2).sum(axis=1)
+    assert (tot[real] == want).all(), "private form does not decrypt to the distances"
+    nat.sanns_profile_enable(ctx.handle, True)
+    for _ in range(3):
+        D.run(ct, key, qids, pk=pks)
+    ph, _ = nat.sanns_profile_read(ctx.handle)
+    nat.sanns_profile_enable(ctx.handle, False)
+    v = Q * len(pts) / dt
+    b = nat.sanns_flood_bits(ctx.handle)
+    log(f"private form: {1e3 * dt:.3f} ms/step, {v / 1e9:.3f} G distances/s "
+        f"(flood 2^{b}); phases {ph}")
+    return {"value": round(v, 1), "unit": UNIT, "ms_per_step": round(1e3 * dt, 4),
+            "cost_vs_batched": round(1e3 * dt / ms_per_step, 3), "flood_bits": b,
+            "schedule": sched.label(),
+            "phases_ms": {k: round(x, 4) for k, x in ph.items()}}
 
 
 def encrypt_pool(ctx, queries, seed, dev):
@@ -544,18 +601,15 @@ def run_serving(args):
         """Requests of the arrival trace; with per_query every request is
         split into single-query requests that share its arrival time."""
         arr = synthdata.gen_arrivals(count, rate, n_dbs=3, max_q=64, seed=seed)
-        reqs, qid = [], 1 << 20
+        reqs = []
         for r in arr:
             name = "ABC"[r.db]
             ct_all = ctA if name == "A" else ctB
             parts = [(i, i + 1) for i in range(r.Q)] if per_query else [(0, r.Q)]
             for a, b in parts:
-                req = serve.Request(r.rid, name, ct_all[a:b],
-                                    np.arange(qid + a, qid + b, dtype=np.uint64), r.k,
-                                    arrival=r.arrival_s)
+                req = serve.Request(r.rid, name, ct_all[a:b], r.k, arrival=r.arrival_s)
                 req.pool_rows = np.arange(a, b) % pool
                 reqs.append(req)
-            qid += r.Q
         return reqs
 
     def distances_of(req):
@@ -668,37 +722,117 @@ def run_fused(args, ctx, db, F, ct1, key, q1, n, d, L, C, N):
                           "traffic_unit": "bytes/launch",
                           "avg_ms": round(fph["mac"], 4),
                           "algorithmic": f"{mac1_bytes} B (resident DB + query NTT "
-                                         "read + NTT-form outputs written)"}}
+                                         "read + NTT-form outputs written)",
+                          "bytes_per_distance": round(mac1_bytes / n, 1),
+                          "modular_mul_acc_per_s": round(2 * d * L * N * C /
+                                                         (fph["mac"] * 1e-3), 1),
+                          "distances_per_s_in_kernel": round(n / (fph["mac"] * 1e-3), 1)}}
     log(f"fused Q=1: p50 {fused['query_p50_ms']} ms, {fused_value / 1e9:.3f} G/s, "
         f"mac {mac1_gbs:.0f} GB/s")
     return fused
 
 
-def cpu_baseline(w, pts, slot, qv, N, L, t):
-    """The oracle, as it stands, on one chunk (8192 slots) of this database
-    for one query: its server stage (products, masks, norm plaintext) timed;
-    its client encryption done first and not timed."""
-    import oracle
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def host_threads() -> int:
+    """Threads this process may run the oracle on: its CPU affinity, capped
+    by OMP_NUM_THREADS when that is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit():
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def _oracle_chunk_inputs(oracle, w, pts, slot, qv, N, L, t, k=0):
     P = oracle.Params(N, oracle.rns_primes(N, L), t)
     assert P.t == t
-    s = synthdata.gen_secret(N, 1)
     d = pts.shape[1]
+    s = synthdata.gen_secret(N, 1)
     a = synthdata.gen_uniform_a(P.qs, N, d, 2)
     e = synthdata.gen_cbd_error(N, d, 2)
     ct = oracle.encrypt_constants(P, s, a, e, [int(x) for x in qv])
-    g, nrm = oracle.chunk_plaintexts(pts, slot, N, 0)
+    return P, ct
+
+
+def cpu_baseline(w, pts, slot, qv, N, L, t):
+    """The oracle, as it stands, on this host's cores (its client encryption
+    is done first and not timed; the server stage -- schoolbook negacyclic
+    products for 2 components x L limbs x d coordinates, masks and the norm
+    plaintext -- is):
+      * all cores: one chunk (N slots) of this database for one query; the
+        workload's rate is N / that time (extrapolated from one of its chunks);
+      * one thread: the same chunk's output at 256 of its N coefficient
+        positions (the oracle's per-coefficient routine), extrapolated to N;
+      * the 10,000 x 128 uint8 linear scan (N = 4096, L = 2, 3 chunks) in
+        full, on all cores and (one chunk, extrapolated x3) on one thread."""
+    import oracle
+    threads = oracle.set_threads(host_threads())
     key = synthdata.gen_mask_key(3)
+    d = pts.shape[1]
+    P, ct = _oracle_chunk_inputs(oracle, w, pts, slot, qv, N, L, t)
+    g, nrm = oracle.chunk_plaintexts(pts, slot, N, 0)
     t0 = time.perf_counter()
     oracle.server_chunk(P, ct, g, nrm, key, 0, 0)
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    log(f"cpu oracle: {dt:.2f}s for one chunk on {threads} threads")
-    return {"value": round(N / dt, 1), "unit": UNIT, "cores": threads, "kind": "oracle",
-            "sample": f"one chunk ({N} slots) of the {len(pts):,} x {d} database, one query: "
-                      "schoolbook negacyclic products for 2 components x "
-                      f"{L} limbs x {d} coordinates, masks and norm plaintext "
-                      "(encryption not timed)",
-            "seconds": round(dt, 2)}
+    dt_all = time.perf_counter() - t0
+    oracle.set_threads(1)
+    js = list(range(0, N, N // 256))
+    t0 = time.perf_counter()
+    oracle.server_coeffs(P, ct, g, nrm, key, 0, 0, js)
+    dt_one = (time.perf_counter() - t0) * N / len(js)
+    log(f"cpu oracle ({cpu_model()}): one chunk {dt_all:.2f}s on {threads} threads, "
+        f"{dt_one:.1f}s on one thread (extrapolated)")
+    # the 10,000 x 128 workload in full
+    w1 = synthdata.WORKLOADS[1]
+    p1 = synthdata.gen_points(w1)
+    q1 = synthdata.gen_queries(w1, 1)[0]
+    t1 = oracle.plain_modulus(w1.N, w1.t_bits)
+    s1 = synthdata.gen_slot_map(len(p1), w1.N, synthdata.SEED_PERM + 1)
+    P1, ct1 = _oracle_chunk_inputs(oracle, w1, p1, s1, q1, w1.N, w1.L, t1)
+    C1 = len(s1) // w1.N
+    chunks = [oracle.chunk_plaintexts(p1, s1, w1.N, k) for k in range(C1)]
+    oracle.set_threads(threads)
+    t0 = time.perf_counter()
+    for k, (gk, nk) in enumerate(chunks):
+        oracle.server_chunk(P1, ct1, gk, nk, key, 0, k)
+    dt1_all = time.perf_counter() - t0
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.server_chunk(P1, ct1, chunks[0][0], chunks[0][1], key, 0, 0)
+    dt1_one = (time.perf_counter() - t0) * C1
+    oracle.set_threads(threads)
+    log(f"cpu oracle, 10K x 128 in full: {dt1_all:.2f}s on {threads} threads, "
+        f"{dt1_one:.1f}s on one thread (one chunk x {C1})")
+    return {"value": round(N / dt_all, 1), "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": f"one chunk ({N} slots) of the {len(pts):,} x {d} database, one query, "
+                      f"on {threads} threads: schoolbook negacyclic products for 2 components "
+                      f"x {L} limbs x {d} coordinates, masks and norm plaintext (encryption "
+                      f"not timed); extrapolated to the database: N / chunk time",
+            "extrapolated": True, "seconds": round(dt_all, 2),
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": round(N / dt_one, 1), "unit": UNIT, "cores": 1,
+                              "sample": f"the same chunk at {len(js)} of its {N} coefficient "
+                                        "positions, extrapolated to N",
+                              "extrapolated": True, "seconds_per_chunk": round(dt_one, 2)},
+            "workload_10Kx128_full": {
+                "distances": len(p1), "chunks": C1, "N": w1.N, "L": w1.L,
+                "all_cores": {"value": round(len(p1) / dt1_all, 1), "unit": UNIT,
+                              "cores": threads, "seconds": round(dt1_all, 2),
+                              "extrapolated": False},
+                "single_thread": {"value": round(len(p1) / dt1_one, 1), "unit": UNIT,
+                                  "cores": 1, "seconds": round(dt1_one, 2),
+                                  "extrapolated": True,
+                                  "sample": f"one of its {C1} chunks, times {C1}"}}}
 
 
 if __name__ == "__main__":

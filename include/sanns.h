@@ -186,6 +186,45 @@ sanns_status sanns_encrypt_query(sanns_ctx *ctx, const int8_t *sk,
                                  const uint64_t *a, const int16_t *e,
                                  uint64_t *ct_out, void *stream);
 
+/* Client randomness drawn from a seed, for tests and examples (the same
+ * definitions are implemented independently by the CPU oracle).  Both draw
+ * from ChaCha20 (RFC 8439 block function) with the 32-byte key
+ * (seed low 32 bits, seed high 32 bits, purpose, 0, 0, 0, 0, 0) as eight
+ * little-endian words; x_j below is the 64-bit word (2n, 2n+1), n = j % 8, of
+ * block j / 8, and X_j the 128-bit integer of words 4(j%4) .. 4(j%4)+3 of
+ * block j / 4.
+ *
+ * Key generation (Section 2.3, private-key AHE; linear-scan protocol step 1,
+ * the client's key): purpose 1, nonce (0, 0, 0); s_j = (x_j mod 3) - 1.
+ *   sk  dev [N] int8 out, in {-1, 0, 1}
+ * Errors: SANNS_E_INVALID, SANNS_E_DEVICE. */
+sanns_status sanns_keygen(sanns_ctx *ctx, uint64_t seed, int8_t *sk, void *stream);
+
+/* Encryption with its randomness drawn from enc_seed (linear-scan protocol
+ * step 2): sanns_encrypt_query with, for query qi and coordinate i,
+ *   a[qi][i][l][j] = X_j mod q_l  (purpose 2, nonce (qi, i, l)),
+ *   e[qi][i][j]    = popcount(bits 0..20 of x_j) - popcount(bits 21..41 of
+ *                    x_j), a centred binomial with eta = 21 (purpose 3,
+ *                    nonce (qi, i, 0)).
+ * A seed must not be reused for two encryptions under one key.  Temporary
+ * device memory for a and e (Q d (8 L + 2) N bytes) is taken from the
+ * stream-ordered allocator.  Arguments as sanns_encrypt_query.  Errors:
+ * SANNS_E_INVALID, SANNS_E_DEVICE. */
+sanns_status sanns_encrypt_query_seeded(sanns_ctx *ctx, const int8_t *sk,
+                                        const int32_t *msgs, uint32_t Q, uint32_t d,
+                                        uint64_t enc_seed, uint64_t *ct_out,
+                                        void *stream);
+
+/* The client's public key for the circuit-private form (Section 2.3): an
+ * encryption of zero pk = (p0, p1) = (-a s + e, a) mod q_l, with a and e drawn
+ * from `seed` as in sanns_encrypt_query_seeded but with purposes 4 and 5
+ * (a: nonce (0, 0, l); e: nonce (0, 0, 0)).
+ *   sk  dev [N] int8
+ *   pk  dev [2][L][N] uint64 out, coefficient form
+ * Errors: SANNS_E_INVALID, SANNS_E_DEVICE. */
+sanns_status sanns_public_key(sanns_ctx *ctx, const int8_t *sk, uint64_t seed,
+                              uint64_t *pk, void *stream);
+
 /* Client decryption to shares (linear-scan protocol steps 4-5): for each of
  * the M ciphertexts, x = c0 + c1*s mod q (exact CRT over the limbs),
  * m = floor((t x + floor(q/2)) / q) mod t, and
@@ -246,6 +285,8 @@ size_t sanns_distances_workspace(const sanns_ctx *ctx, const sanns_db *db,
  * context under the call's pointers and sizes and replays it on later calls
  * with the same ones (new contents of every device buffer, query_ids
  * included, are picked up; the mask_key bytes are part of the cache key).
+ * A context caches at most 32 such graphs; beyond that the least recently
+ * launched one is destroyed once its last launch has completed.
  * SANNS_MODE_PERSISTENT runs the whole call as one launch of a work-queue
  * kernel (after a reset of its control words in the workspace): query NTTs
  * and mask rows first, then the multiply-accumulate tiles, then INTT + mask,
@@ -259,6 +300,48 @@ sanns_status sanns_distances(sanns_ctx *ctx, const sanns_db *db,
                              const uint32_t *work, uint32_t M, int mode,
                              uint64_t *ct_out, uint32_t *server_share,
                              void *workspace, size_t ws_bytes, void *stream);
+
+/* Circuit-private form of sanns_distances (Section 2.3: the server's result
+ * must reveal nothing beyond its plaintext, by noise flooding; Section 5
+ * "Parameters", statistical circuit privacy).  Every output ciphertext f of
+ * query qi, chunk k additionally receives a fresh encryption of zero under
+ * that query's public key pk = (p0, p1), and c0 a flood:
+ *   ct_out[m] = f + (p0 u + e1 + F, p1 u + e2)
+ * with u ternary, e1, e2 centred binomial (eta = 21) and F uniform in
+ * [-2^b, 2^b), drawn from ChaCha20 under mask_key with the mask stream's nonce
+ * (query id low word, high word, k) and block counter s 2^24 + block for
+ * stream s: 1 u_j = (x_j mod 3) - 1, 2 e1_j and 3 e2_j = popcount(bits 0..20
+ * of x_j) - popcount(bits 21..41 of x_j), x_j the 64-bit word (2n, 2n+1),
+ * n = j % 8, of block j / 8; 4 F_j = (Y_j mod 2^(b+1)) - 2^b, Y_j the 256-bit
+ * integer of words 8(j%2) .. 8(j%2)+7 of block j / 2.  The re-randomisation
+ * replaces c1 = sum_i a_i g_i (which the client could relate to the points)
+ * by a fresh RLWE sample; the flood hides the product's noise.  Decryption is
+ * unchanged while |noise| + 2^b stays below Delta / 2 - t.
+ *   pk          dev [Q][2][L][N] uint64, coefficient form, residues < q_l
+ *               (checked on the device like ct_in)
+ *   flood_bits  b, at most sanns_flood_bits(ctx); 0 selects that maximum
+ *   other arguments as sanns_distances; mode SANNS_MODE_FUSED or
+ *   SANNS_MODE_BATCHED; the workspace from sanns_distances_cp_workspace.
+ * The server shares are those of sanns_distances.  Errors: those of
+ * sanns_distances; SANNS_E_RANGE for flood_bits above the maximum;
+ * SANNS_E_INVALID for another mode. */
+sanns_status sanns_distances_cp(sanns_ctx *ctx, const sanns_db *db,
+                                const uint64_t *ct_in, uint32_t Q,
+                                const uint8_t *mask_key,
+                                const uint64_t *query_ids, const uint64_t *pk,
+                                uint32_t flood_bits, const uint32_t *work,
+                                uint32_t M, int mode, uint64_t *ct_out,
+                                uint32_t *server_share, void *workspace,
+                                size_t ws_bytes, void *stream);
+
+/* Workspace bytes of sanns_distances_cp (that of sanns_distances plus the
+ * public keys' NTT form, Q 2 L N 8 bytes). */
+size_t sanns_distances_cp_workspace(const sanns_ctx *ctx, const sanns_db *db,
+                                    uint32_t Q, uint32_t M, int mode);
+
+/* Largest flood width b of the context: the largest b with 2^b <= Delta / 4,
+ * Delta = floor(q / t) (0 for a null context). */
+uint32_t sanns_flood_bits(const sanns_ctx *ctx);
 
 /* Synchronise `stream` and return (and clear) the context's device error
  * word: SANNS_E_RANGE if, since the last call, an input residue was >= q_l
@@ -293,7 +376,9 @@ sanns_status sanns_set_schedule(sanns_ctx *ctx, int lds_variant, int qt, int ct)
                                    signed digits (0 for other schedules)    */
 #define SANNS_PHASE_SUMS 5      /* SANNS_SCHEDULE_MFMA: slot-major sums ->
                                    NTT-form outputs (0 for other schedules) */
-#define SANNS_N_PHASES 6
+#define SANNS_PHASE_RERAND 6    /* sanns_distances_cp: public keys' NTT and
+                                   u pk added to the NTT-form outputs       */
+#define SANNS_N_PHASES 7
 
 /* Per-phase timing of the fused form (tracing aid).  While enabled,
  * sanns_distances in SANNS_MODE_FUSED or SANNS_MODE_BATCHED records a HIP

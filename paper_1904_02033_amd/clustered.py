@@ -90,6 +90,13 @@ class ClusteredServer:
         self.cdb = stage.encode_db(ctx, centers, self.center_slot)
         self.key_points, self.key_centers = key_points, key_centers
         self.n_points = len(points)
+        self.next_qid = 0
+
+    def take_qids(self, Q: int) -> np.ndarray:
+        """Q query ids never used before under this index's two mask keys."""
+        out = np.arange(self.next_qid, self.next_qid + Q, dtype=np.uint64)
+        self.next_qid += Q
+        return out
 
     # ---------------------------------------------------------------- phase 1
     def center_distances(self, ct: torch.Tensor, qids: torch.Tensor,

@@ -50,6 +50,13 @@ struct MaskKey {
   uint32_t k[8];
 };
 
+// Flooding of the circuit-private form: width b (flood uniform in
+// [-2^b, 2^b)) and 2^b mod q_l per limb.
+struct CpConst {
+  uint64_t twob[kMaxLimbs];
+  int b;
+};
+
 // Arguments of the persistent whole-batch kernel.
 struct PersistArgs {
   const uint64_t* ct_in;    // [Q][d][2][L][N] coefficient form

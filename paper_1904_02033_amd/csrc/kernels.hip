@@ -260,6 +260,160 @@ k_intt_mask(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
 }
 
 // --------------------------------------------------------------------------
+// circuit privacy: each output gets a fresh encryption of zero under its
+// query's public key pk = (p0, p1),  (p0 u + e1 + flood, p1 u + e2),  with
+// u ternary, e1 and e2 centred binomial (eta = 21) and the flood uniform in
+// [-2^b, 2^b), all drawn from the server's mask key and the output's mask
+// nonce (query id, chunk) at block counters s 2^24 + block for streams
+// s = 1 (u), 2 (e1), 3 (e2), 4 (flood)
+// --------------------------------------------------------------------------
+
+constexpr uint32_t kCpStreamU = 1u << 24, kCpStreamE1 = 2u << 24, kCpStreamE2 = 3u << 24,
+                   kCpStreamFlood = 4u << 24;
+
+__device__ __forceinline__ uint64_t word64_of(const uint32_t (&o)[16], int n) {
+  return (uint64_t)o[2 * n] | (uint64_t)o[2 * n + 1] << 32;
+}
+
+__device__ __forceinline__ int cbd21(uint64_t x) {
+  return __popcll(x & 0x1FFFFFull) - __popcll((x >> 21) & 0x1FFFFFull);
+}
+
+__device__ __forceinline__ uint64_t lift_small(int x, uint64_t q) {
+  return x < 0 ? q - (uint64_t)(-x) : (uint64_t)x;
+}
+
+// (X mod 2^(b+1)) - 2^b  mod q, X the 256-bit little-endian integer w[0..7]:
+// Horner over the 32-bit words from the top kept word down (r 2^32 by a
+// Shoup product with 2^32 mod q; q > 2^32 keeps r + w below 2q).
+__device__ __forceinline__ uint64_t flood_residue(const uint32_t* w, int b, uint64_t twob,
+                                                  const DigitConst& D, uint64_t q) {
+  const int bits = b + 1;
+  uint64_t r = 0;
+  for (int i = (bits - 1) >> 5; i >= 0; --i) {
+    const int keep = bits - 32 * i;
+    const uint32_t x = keep >= 32 ? w[i] : (w[i] & ((1u << keep) - 1u));
+    r = shoup(r, D.w32, D.w32p, q) + x;
+    if (r >= q) r -= q;
+  }
+  return submod(r, twob, q);
+}
+
+// Workgroup per (output m, limb l): u in NTT form (generated cooperatively
+// into LDS, then transformed), times the NTT form of the query's public key,
+// added to both NTT-form components of ct_out.
+template <int LOGN>
+__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
+k_rerand(MaskKey K, const uint64_t* __restrict__ qids, const uint32_t* __restrict__ work, int C,
+         int L, const uint64_t* __restrict__ pk_ntt, uint64_t* __restrict__ ct, PrimeSet ps,
+         TwSet tws) {
+  extern __shared__ uint64_t lds[];
+  constexpr int N = NttShape<LOGN>::N, T = NttShape<LOGN>::T;
+  const int tid = threadIdx.x, l = blockIdx.x % L, m = blockIdx.x / L;
+  int qi, k;
+  work_pair(work, m, C, qi, k);
+  const uint64_t id = qids[qi];
+  int8_t* ub = reinterpret_cast<int8_t*>(lds);
+  for (int b = tid; b < N / 8; b += T) {
+    uint32_t o[16];
+    chacha_block(K, kCpStreamU + (uint32_t)b, (uint32_t)id, (uint32_t)(id >> 32), (uint32_t)k, o);
+#pragma unroll
+    for (int n = 0; n < 8; ++n) ub[8 * b + n] = (int8_t)((int)(word64_of(o, n) % 3u) - 1);
+  }
+  __syncthreads();
+  const Prime& P = ps.p[l];
+  uint64_t v[16];
+#pragma unroll
+  for (int a = 0; a < 16; ++a) v[a] = lift_small(ub[coef_index<LOGN>(tid, a)], P.q);
+  __syncthreads();  // the transform reuses the LDS
+  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P);
+  const uint64_t* pk0 = pk_ntt + ((size_t)(2 * qi) * L + l) * N;
+  const uint64_t* pk1 = pk_ntt + ((size_t)(2 * qi + 1) * L + l) * N;
+  uint64_t* c0 = ct + ((size_t)(2 * m) * L + l) * N;
+  uint64_t* c1 = ct + ((size_t)(2 * m + 1) * L + l) * N;
+#pragma unroll
+  for (int a = 0; a < 16; ++a) {
+    const int w = ntt_slot<LOGN>(tid, a);
+    c0[w] = addmod(c0[w], mulmod(v[a], pk0[w], P), P.q);
+    c1[w] = addmod(c1[w], mulmod(v[a], pk1[w], P), P.q);
+  }
+}
+
+// k_intt_mask with the re-randomisation's coefficient-form terms: e1, the
+// flood and Delta [norm - r]_t on c0, e2 on c1.  The errors are generated into
+// LDS for the whole polynomial; the flood (one ChaCha20 block per two
+// coefficients) a quarter of the coefficients at a time.
+// Four waves per SIMD: the flood's ChaCha20 state beside the 16 residues
+// needs more registers than k_intt_mask's bound leaves (it spilled at six).
+template <int LOGN>
+__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
+k_intt_mask_cp(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
+               const uint32_t* __restrict__ norms, const uint32_t* __restrict__ work, int C,
+               int L, uint32_t t, MaskKey K, const uint64_t* __restrict__ qids, CpConst cp,
+               DigitSet ds, PrimeSet ps, TwSet tws) {
+  extern __shared__ uint64_t lds[];
+  constexpr int N = NttShape<LOGN>::N, T = NttShape<LOGN>::T;
+  const int tid = threadIdx.x, p = blockIdx.x;
+  const int l = p % L, c = (p / L) & 1, m = p / (2 * L);
+  int qi, k;
+  work_pair(work, m, C, qi, k);
+  const uint64_t id = qids[qi];
+  const uint32_t n0 = (uint32_t)id, n1 = (uint32_t)(id >> 32), n2 = (uint32_t)k;
+  const Prime& P = ps.p[l];
+  uint64_t* buf = ct + (size_t)p * N;
+  uint64_t v[16];
+#pragma unroll
+  for (int a = 0; a < 16; ++a) v[a] = buf[ntt_slot<LOGN>(tid, a)];
+  ntt_inv<LOGN>(v, lds, tid, tws.tw[l] + N, P);
+  __syncthreads();  // the transform's LDS is free
+  int8_t* eb = reinterpret_cast<int8_t*>(lds);
+  for (int b = tid; b < N / 8; b += T) {
+    uint32_t o[16];
+    chacha_block(K, (c == 0 ? kCpStreamE1 : kCpStreamE2) + (uint32_t)b, n0, n1, n2, o);
+#pragma unroll
+    for (int n = 0; n < 8; ++n) eb[8 * b + n] = (int8_t)cbd21(word64_of(o, n));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 16; ++a)
+    v[a] = addmod(v[a], lift_small(eb[coef_index<LOGN>(tid, a)], P.q), P.q);
+  if (c == 0) {
+    const uint32_t* nrm = norms + (size_t)k * N;
+    const uint32_t* r = share + (size_t)m * N;
+#pragma unroll
+    for (int a = 0; a < 16; ++a) {
+      const int j = coef_index<LOGN>(tid, a);
+      const uint32_t pn = nrm[j], rj = r[j];
+      const uint64_t mv = pn >= rj ? pn - rj : pn + t - rj;
+      v[a] = addmod(v[a], shoup(mv, P.delta, P.deltap, P.q), P.q);
+    }
+    uint64_t* fb = lds + N / 8;  // after the error bytes
+    const DigitConst& D = ds.c[l];
+    const uint64_t twob = cp.twob[l];
+    constexpr int Nq = N / 4;
+#pragma unroll 1
+    for (int rd = 0; rd < 4; ++rd) {
+      for (int h = tid; h < Nq / 2; h += T) {
+        uint32_t o[16];
+        chacha_block(K, kCpStreamFlood + (uint32_t)(rd * (Nq / 2) + h), n0, n1, n2, o);
+        fb[2 * h] = flood_residue(o, cp.b, twob, D, P.q);
+        fb[2 * h + 1] = flood_residue(o + 8, cp.b, twob, D, P.q);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int a = 0; a < 16; ++a) {
+        const int j = coef_index<LOGN>(tid, a) - rd * Nq;
+        if (j >= 0 && j < Nq) v[a] = addmod(v[a], fb[j], P.q);
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();  // every thread has read its inputs before any overwrite
+#pragma unroll
+  for (int a = 0; a < 16; ++a) buf[coef_index<LOGN>(tid, a)] = v[a];
+}
+
+// --------------------------------------------------------------------------
 // fused multiply-accumulate over the resident database
 // --------------------------------------------------------------------------
 
@@ -1067,6 +1221,92 @@ k_sk_ntt(const int8_t* __restrict__ sk, uint64_t* __restrict__ out, PrimeSet ps,
   for (int a = 0; a < 16; ++a) out[(size_t)l * N + ntt_slot<LOGN>(tid, a)] = v[a];
 }
 
+// --------------------------------------------------------------------------
+// client randomness drawn from a seed (key generation and encryption helpers):
+// ChaCha20 with key (seed low word, seed high word, purpose, 0, ..., 0),
+// purpose 1 secret key, 2 uniform component a, 3 error e, 4 and 5 the same for
+// the public key
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ MaskKey client_key(uint64_t seed, uint32_t purpose) {
+  MaskKey K;
+  K.k[0] = (uint32_t)seed;
+  K.k[1] = (uint32_t)(seed >> 32);
+  K.k[2] = purpose;
+#pragma unroll
+  for (int i = 3; i < 8; ++i) K.k[i] = 0;
+  return K;
+}
+
+// (w3 2^96 + w2 2^64 + w1 2^32 + w0) mod q for q < 2^54: Horner steps of one
+// byte, every intermediate below 2^62.
+__device__ uint64_t mod_q_128(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint64_t q) {
+  const uint32_t w[4] = {w3, w2, w1, w0};
+  uint64_t r = 0;
+  for (int a = 0; a < 4; ++a)
+    for (int sh = 24; sh >= 0; sh -= 8) r = ((r << 8) | ((w[a] >> sh) & 0xFFu)) % q;
+  return r;
+}
+
+// Thread per block b (coefficients 8b .. 8b+7): s_j = (x_j mod 3) - 1 with
+// x_j the 64-bit word j % 8 of block j / 8, nonce (0, 0, 0).
+__global__ void __launch_bounds__(256) k_keygen(uint64_t seed, int N, int8_t* __restrict__ sk) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= N / 8) return;
+  const MaskKey K = client_key(seed, 1);
+  uint32_t o[16];
+  chacha_block(K, (uint32_t)b, 0u, 0u, 0u, o);
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+    const uint64_t x = (uint64_t)o[2 * n] | (uint64_t)o[2 * n + 1] << 32;
+    sk[8 * b + n] = (int8_t)((int)(x % 3u) - 1);
+  }
+}
+
+// Thread per (query x coordinate qd, limb l, block b): a_j for j = 4b .. 4b+3
+// is the 128-bit integer of words 4(j%4) .. 4(j%4)+3 of block b, nonce
+// (query, coordinate, limb), reduced mod q_l.  a: [Qd][L][N].
+__global__ void __launch_bounds__(256)
+k_sample_a(uint64_t seed, uint32_t purpose, int d, int L, int N, long total, PrimeSet ps,
+           uint64_t* __restrict__ a) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int nb = N / 4;
+  const int b = (int)(g % nb);
+  const long r = g / nb;
+  const int l = (int)(r % L);
+  const long qd = r / L;
+  const MaskKey K = client_key(seed, purpose);
+  uint32_t o[16];
+  chacha_block(K, (uint32_t)b, (uint32_t)(qd / d), (uint32_t)(qd % d), (uint32_t)l, o);
+  const uint64_t q = ps.p[l].q;
+  uint64_t* row = a + ((size_t)qd * L + l) * N + 4 * b;
+#pragma unroll
+  for (int n = 0; n < 4; ++n)
+    row[n] = mod_q_128(o[4 * n], o[4 * n + 1], o[4 * n + 2], o[4 * n + 3], q);
+}
+
+// Thread per (query x coordinate qd, block b): centred binomial error
+// (eta = 21) e_j = popcount(bits 0..20 of x_j) - popcount(bits 21..41 of x_j),
+// x_j the 64-bit word j % 8 of block j / 8, nonce (query, coordinate, 0).
+__global__ void __launch_bounds__(256)
+k_sample_e(uint64_t seed, uint32_t purpose, int d, int N, long total, int16_t* __restrict__ e) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int nb = N / 8;
+  const int b = (int)(g % nb);
+  const long qd = g / nb;
+  const MaskKey K = client_key(seed, purpose);
+  uint32_t o[16];
+  chacha_block(K, (uint32_t)b, (uint32_t)(qd / d), (uint32_t)(qd % d), 0u, o);
+  int16_t* row = e + (size_t)qd * N + 8 * b;
+#pragma unroll
+  for (int n = 0; n < 8; ++n) {
+    const uint64_t x = (uint64_t)o[2 * n] | (uint64_t)o[2 * n + 1] << 32;
+    row[n] = (int16_t)(__popcll(x & 0x1FFFFFull) - __popcll((x >> 21) & 0x1FFFFFull));
+  }
+}
+
 // Workgroup per (query, coordinate, limb): c1 = a, c0 = -a s + e + Delta m.
 template <int LOGN>
 __global__ void __launch_bounds__(NttShape<LOGN>::T)
@@ -1563,6 +1803,62 @@ hipError_t launch_sk_ntt(const int8_t* sk, uint64_t* out, int logN, int L, const
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_rerand(const MaskKey& K, const uint64_t* qids, const uint32_t* work, int C,
+                         int M, int L, int logN, const uint64_t* pk_ntt, uint64_t* ct,
+                         const PrimeSet& ps, const TwSet& tws, hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  switch (logN) {
+#define SANNS_CASE(LG)                                                                    \
+  case LG:                                                                                \
+    ntt_launch<LG>(k_rerand<LG>, (unsigned)(M * L), st, K, qids, work, C, L, pk_ntt, ct, ps, \
+                   tws);                                                                  \
+    break;
+    SANNS_LOGN_CASES(SANNS_CASE)
+#undef SANNS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_intt_mask_cp(uint64_t* ct, const uint32_t* share, const uint32_t* norms,
+                               const uint32_t* work, int C, int M, int logN, int L, uint32_t t,
+                               const MaskKey& K, const uint64_t* qids, const CpConst& cp,
+                               const DigitSet& ds, const PrimeSet& ps, const TwSet& tws,
+                               hipStream_t st) {
+  if (M <= 0) return hipSuccess;
+  switch (logN) {
+#define SANNS_CASE(LG)                                                                       \
+  case LG:                                                                                   \
+    ntt_launch<LG>(k_intt_mask_cp<LG>, (unsigned)(M * 2 * L), st, ct, share, norms, work, C, L, \
+                   t, K, qids, cp, ds, ps, tws);                                             \
+    break;
+    SANNS_LOGN_CASES(SANNS_CASE)
+#undef SANNS_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_keygen(uint64_t seed, int N, int8_t* sk, hipStream_t st) {
+  const int nb = N / 8;
+  hipLaunchKernelGGL(k_keygen, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, seed, N, sk);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_enc(uint64_t seed, uint32_t purpose_a, uint32_t purpose_e, int Qd,
+                             int d, int L, int N, const PrimeSet& ps, uint64_t* a, int16_t* e,
+                             hipStream_t st) {
+  if (Qd <= 0) return hipSuccess;
+  const long ta = (long)Qd * L * (N / 4), te = (long)Qd * (N / 8);
+  hipLaunchKernelGGL(k_sample_a, dim3((unsigned)((ta + 255) / 256)), dim3(256), 0, st, seed,
+                     purpose_a, d, L, N, ta, ps, a);
+  hipLaunchKernelGGL(k_sample_e, dim3((unsigned)((te + 255) / 256)), dim3(256), 0, st, seed,
+                     purpose_e, d, N, te, e);
   return hipGetLastError();
 }
 

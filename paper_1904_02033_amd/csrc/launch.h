@@ -110,6 +110,23 @@ hipError_t launch_encode_ntt(const int16_t* gt, uint2* dbres, int k0, int nk, in
                              hipStream_t st);
 hipError_t launch_sk_ntt(const int8_t* sk, uint64_t* out, int logN, int L, const PrimeSet& ps,
                          const TwSet& tws, hipStream_t st);
+// Client randomness from a seed: ternary secret [N]; uniform a [Qd][L][N]
+// and errors e [Qd][N] of Qd = Q d encrypted coordinates.
+hipError_t launch_keygen(uint64_t seed, int N, int8_t* sk, hipStream_t st);
+hipError_t launch_sample_enc(uint64_t seed, uint32_t purpose_a, uint32_t purpose_e, int Qd,
+                             int d, int L, int N, const PrimeSet& ps, uint64_t* a, int16_t* e,
+                             hipStream_t st);
+// Circuit privacy: u pk added to the NTT-form outputs (pk_ntt [Q][2][L][N] in
+// NTT storage order), then the inverse transform with e1, flood and the mask
+// plaintext on c0 and e2 on c1.
+hipError_t launch_rerand(const MaskKey& K, const uint64_t* qids, const uint32_t* work, int C,
+                         int M, int L, int logN, const uint64_t* pk_ntt, uint64_t* ct,
+                         const PrimeSet& ps, const TwSet& tws, hipStream_t st);
+hipError_t launch_intt_mask_cp(uint64_t* ct, const uint32_t* share, const uint32_t* norms,
+                               const uint32_t* work, int C, int M, int logN, int L, uint32_t t,
+                               const MaskKey& K, const uint64_t* qids, const CpConst& cp,
+                               const DigitSet& ds, const PrimeSet& ps, const TwSet& tws,
+                               hipStream_t st);
 hipError_t launch_encrypt(const uint64_t* a, const int16_t* e, const int32_t* msgs,
                           const uint64_t* sk_ntt, uint64_t* ct, int Qd, int L, int logN,
                           uint32_t t, const PrimeSet& ps, const TwSet& tws, hipStream_t st);

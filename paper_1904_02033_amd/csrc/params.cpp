@@ -221,6 +221,33 @@ DecodeConst decode_consts(const std::vector<uint64_t>& qs, uint64_t t) {
   return D;
 }
 
+int delta_bits(const std::vector<uint64_t>& qs, uint64_t t) {
+  std::vector<uint32_t> qw = {1};
+  for (uint64_t q : qs) qw = mw_mul(qw, q);
+  // long division of the words by t < 2^31, most significant word first
+  uint64_t rem = 0;
+  std::vector<uint32_t> quo(qw.size(), 0);
+  for (size_t i = qw.size(); i-- > 0;) {
+    const uint64_t cur = (rem << 32) | qw[i];
+    quo[i] = (uint32_t)(cur / t);
+    rem = cur % t;
+  }
+  int bits = 0;
+  for (size_t i = quo.size(); i-- > 0;)
+    if (quo[i]) {
+      bits = 32 * (int)i;
+      for (uint32_t top = quo[i]; top; top >>= 1) ++bits;
+      break;
+    }
+  return bits;
+}
+
+uint64_t pow2_mod(int e, uint64_t q) {
+  uint64_t r = 1 % q;
+  for (int i = 0; i < e; ++i) r = (uint64_t)(((u128)r << 1) % q);
+  return r;
+}
+
 int log2q_bits(const std::vector<uint64_t>& qs) {
   std::vector<uint32_t> qw = {1};
   for (uint64_t q : qs) qw = mw_mul(qw, q);

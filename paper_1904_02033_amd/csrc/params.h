@@ -32,6 +32,11 @@ std::vector<uint64_t> delta_mod_limbs(const std::vector<uint64_t>& qs, uint64_t 
 
 DecodeConst decode_consts(const std::vector<uint64_t>& qs, uint64_t t);
 
+// Bit length of Delta = floor(prod q_l / t), t < 2^31.
+int delta_bits(const std::vector<uint64_t>& qs, uint64_t t);
+// 2^e mod q.
+uint64_t pow2_mod(int e, uint64_t q);
+
 // log2 of prod q_l, rounded up to whole bits.
 int log2q_bits(const std::vector<uint64_t>& qs);
 

@@ -22,6 +22,7 @@ namespace {
 
 thread_local std::string g_last_error;
 
+
 sanns_status fail(sanns_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -51,6 +52,8 @@ struct GraphKey {
   const void* share;
   const void* ws;
   int qt, ct, lds, n_tiles, table, persist;
+  const void* pk;
+  uint32_t flood_bits;
   uint32_t key[8];
   bool operator<(const GraphKey& o) const { return std::memcmp(this, &o, sizeof *this) < 0; }
 };
@@ -69,13 +72,27 @@ struct sanns_ctx {
   uint64_t tone = 0;  // floor(2^64 / t)
   uint64_t* d_tw = nullptr;
   uint32_t* d_err = nullptr;
+  int flood_bits_max = 0;   // largest b with 2^b <= Delta / 4 (circuit-private form)
   hipStream_t cap_stream = nullptr;
   std::mutex mu;
-  std::map<GraphKey, hipGraphExec_t> graphs;
-  // pinned staging for host-built schedules
-  void* staging = nullptr;
-  size_t staging_bytes = 0;
-  hipEvent_t staging_done = nullptr;
+  // captured batched sequences, least recently used evicted beyond kMaxGraphs
+  struct CachedGraph {
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // recorded after each launch; awaited before destruction
+    uint64_t last_use = 0;
+  };
+  std::map<GraphKey, CachedGraph> graphs;
+  uint64_t graph_clock = 0;
+  // pinned staging for host-built schedules: a ring of buffers, each reused
+  // once the copy out of it has completed, so that callers on different
+  // streams do not wait for each other's copies
+  struct Staging {
+    void* buf = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+  };
+  Staging staging[4];
+  int staging_next = 0;
   // schedule override (0 = automatic)
   int force_qt = 0, force_ct = 0, force_lds = 0, force_persist = 0;
   // per-phase profiling: one event pair per phase and call
@@ -96,6 +113,7 @@ int log2u(uint32_t x) {
 }
 
 const int kDefaultLdsVariant = 22;  // fastest at 1M x 128, 64 queries
+const size_t kMaxGraphs = 32;       // cached graph execs per context
 
 const int kLogqCap[] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 27, 54, 109, 218, 438, 881};
 
@@ -231,31 +249,48 @@ std::vector<int32_t> build_tiles(const uint32_t* work, uint32_t M, int qt, int c
   return out;
 }
 
-// Copy host bytes to device memory on `st` through the context's pinned
-// staging buffer (the previous copy out of it is awaited first).
+// Copy host bytes to device memory on `st` through one of the context's
+// pinned staging buffers: the first, from the ring position on, whose last
+// copy has completed (or, when all are busy, the one at the ring position,
+// after its copy completes).
 sanns_status stage_upload(sanns_ctx* ctx, void* dst, const void* src, size_t bytes,
                           hipStream_t st) {
   if (!bytes) return SANNS_OK;
-  HIP_TRY(hipEventSynchronize(ctx->staging_done));
-  if (bytes > ctx->staging_bytes) {
-    if (ctx->staging) HIP_TRY(hipHostFree(ctx->staging));
-    ctx->staging = nullptr;
-    ctx->staging_bytes = 0;
-    HIP_TRY(hipHostMalloc(&ctx->staging, bytes, hipHostMallocDefault));
-    ctx->staging_bytes = bytes;
+  const int K = (int)(sizeof ctx->staging / sizeof ctx->staging[0]);
+  int pick = -1;
+  for (int i = 0; i < K && pick < 0; ++i) {
+    const int j = (ctx->staging_next + i) % K;
+    const hipError_t q = hipEventQuery(ctx->staging[j].done);
+    if (q == hipSuccess) pick = j;
+    else if (q != hipErrorNotReady) return fail(SANNS_E_DEVICE, "staging: %s", hipGetErrorString(q));
   }
-  std::memcpy(ctx->staging, src, bytes);
-  HIP_TRY(hipMemcpyAsync(dst, ctx->staging, bytes, hipMemcpyHostToDevice, st));
-  HIP_TRY(hipEventRecord(ctx->staging_done, st));
+  if (pick < 0) {
+    pick = ctx->staging_next;
+    HIP_TRY(hipEventSynchronize(ctx->staging[pick].done));
+  }
+  sanns_ctx::Staging& S = ctx->staging[pick];
+  ctx->staging_next = (pick + 1) % K;
+  if (bytes > S.bytes) {
+    if (S.buf) HIP_TRY(hipHostFree(S.buf));
+    S.buf = nullptr;
+    S.bytes = 0;
+    HIP_TRY(hipHostMalloc(&S.buf, bytes, hipHostMallocDefault));
+    S.bytes = bytes;
+  }
+  std::memcpy(S.buf, src, bytes);
+  HIP_TRY(hipMemcpyAsync(dst, S.buf, bytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(S.done, st));
   return SANNS_OK;
 }
 
 struct WsLayout {
-  size_t qntt, tiles, work, tmp, ctrl, qdig, sums, total;
+  size_t qntt, tiles, work, tmp, ctrl, qdig, sums, pkntt, total;
 };
 
-// mfma: the call runs the matrix-core schedule (query digits and sums regions).
-WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M, bool mfma) {
+// mfma: the call runs the matrix-core schedule (query digits and sums regions);
+// cp: the circuit-private form (the public keys' NTT form).
+WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M, bool mfma,
+                   bool cp = false) {
   const size_t N = ctx->p.N, L = ctx->p.L;
   WsLayout w;
   size_t off = 0;
@@ -276,6 +311,8 @@ WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M, boo
     w.sums = off;
     off += align256(mfma_sums_bytes((int)Q, (int)((M + Q - 1) / Q), (int)L, ctx->logN));
   }
+  w.pkntt = off;
+  if (cp) off += align256((size_t)Q * 2 * L * N * 8);
   w.total = off;
   return w;
 }
@@ -334,6 +371,7 @@ extern "C" sanns_status sanns_ctx_create(const sanns_params* p, int device, sann
       tw_all.insert(tw_all.end(), tw.begin(), tw.end());
     }
     ctx->dec = host::decode_consts(qs, p->t);
+    ctx->flood_bits_max = host::delta_bits(qs, p->t) - 3;
   } catch (const std::exception& e) {
     delete ctx;
     return fail(SANNS_E_PARAMS, "%s", e.what());
@@ -349,8 +387,10 @@ extern "C" sanns_status sanns_ctx_create(const sanns_params* p, int device, sann
   if (e == hipSuccess) e = hipMalloc(&ctx->d_err, sizeof(uint32_t));
   if (e == hipSuccess) e = hipMemset(ctx->d_err, 0, sizeof(uint32_t));
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->staging_done, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(ctx->staging_done, ctx->cap_stream);
+  for (auto& S : ctx->staging) {
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(S.done, ctx->cap_stream);
+  }
   if (e != hipSuccess) {
     sanns_ctx_destroy(ctx);
     return fail(SANNS_E_DEVICE, "context setup: %s", hipGetErrorString(e));
@@ -364,11 +404,17 @@ extern "C" sanns_status sanns_ctx_create(const sanns_params* p, int device, sann
 extern "C" void sanns_ctx_destroy(sanns_ctx* ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
-  for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : ctx->graphs) {
+    if (kv.second.done) (void)hipEventSynchronize(kv.second.done);
+    (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.done) (void)hipEventDestroy(kv.second.done);
+  }
   drop_profile_events(ctx);
-  if (ctx->staging_done) (void)hipEventSynchronize(ctx->staging_done);
-  if (ctx->staging) (void)hipHostFree(ctx->staging);
-  if (ctx->staging_done) (void)hipEventDestroy(ctx->staging_done);
+  for (auto& S : ctx->staging) {
+    if (S.done) (void)hipEventSynchronize(S.done);
+    if (S.buf) (void)hipHostFree(S.buf);
+    if (S.done) (void)hipEventDestroy(S.done);
+  }
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->d_tw) (void)hipFree(ctx->d_tw);
   if (ctx->d_err) (void)hipFree(ctx->d_err);
@@ -529,6 +575,65 @@ extern "C" sanns_status sanns_encrypt_query(sanns_ctx* ctx, const int8_t* sk,
   return SANNS_OK;
 }
 
+extern "C" sanns_status sanns_keygen(sanns_ctx* ctx, uint64_t seed, int8_t* sk, void* stream) {
+  if (!ctx || !sk) return fail(SANNS_E_INVALID, "null argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(launch_keygen(seed, (int)ctx->p.N, sk, (hipStream_t)stream));
+  return SANNS_OK;
+}
+
+extern "C" sanns_status sanns_encrypt_query_seeded(sanns_ctx* ctx, const int8_t* sk,
+                                                   const int32_t* msgs, uint32_t Q, uint32_t d,
+                                                   uint64_t enc_seed, uint64_t* ct_out,
+                                                   void* stream) {
+  if (!ctx || !sk || !msgs || !ct_out) return fail(SANNS_E_INVALID, "null argument");
+  if (Q == 0 || d == 0 || d > SANNS_MAX_D) return fail(SANNS_E_INVALID, "bad Q or d");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t N = ctx->p.N, L = ctx->p.L;
+  const size_t Qd = (size_t)Q * d;
+  uint64_t* a = nullptr;
+  int16_t* e = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&a, Qd * L * N * 8, st));
+  hipError_t err = hipMallocAsync((void**)&e, Qd * N * 2, st);
+  if (err == hipSuccess)
+    err = launch_sample_enc(enc_seed, 2, 3, (int)Qd, (int)d, (int)L, (int)N, ctx->ps, a, e, st);
+  sanns_status s = SANNS_OK;
+  if (err == hipSuccess)
+    s = sanns_encrypt_query(ctx, sk, msgs, Q, d, a, e, ct_out, stream);
+  else
+    s = fail(SANNS_E_DEVICE, "seeded encryption: %s", hipGetErrorString(err));
+  if (e) (void)hipFreeAsync(e, st);
+  (void)hipFreeAsync(a, st);
+  return s;
+}
+
+extern "C" sanns_status sanns_public_key(sanns_ctx* ctx, const int8_t* sk, uint64_t seed,
+                                         uint64_t* pk, void* stream) {
+  if (!ctx || !sk || !pk) return fail(SANNS_E_INVALID, "null argument");
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t N = ctx->p.N, L = ctx->p.L;
+  // an encryption of zero whose a and e come from purposes 4 and 5
+  char* tmp = nullptr;
+  const size_t a_bytes = (size_t)L * N * 8, e_bytes = (size_t)N * 2;
+  HIP_TRY(hipMallocAsync((void**)&tmp, a_bytes + e_bytes + 256 + L * N * 8, st));
+  uint64_t* a = (uint64_t*)tmp;
+  int16_t* e = (int16_t*)(tmp + a_bytes);
+  int32_t* zero = (int32_t*)(tmp + a_bytes + e_bytes);
+  uint64_t* sk_ntt = (uint64_t*)(tmp + a_bytes + e_bytes + 256);
+  hipError_t err = hipMemsetAsync(zero, 0, sizeof(int32_t), st);
+  if (err == hipSuccess)
+    err = launch_sample_enc(seed, 4, 5, 1, 1, (int)L, (int)N, ctx->ps, a, e, st);
+  if (err == hipSuccess) err = launch_sk_ntt(sk, sk_ntt, ctx->logN, (int)L, ctx->ps, ctx->tws, st);
+  if (err == hipSuccess)
+    err = launch_encrypt(a, e, zero, sk_ntt, pk, 1, (int)L, ctx->logN, (uint32_t)ctx->p.t,
+                         ctx->ps, ctx->tws, st);
+  (void)hipFreeAsync(tmp, st);
+  if (err != hipSuccess) return fail(SANNS_E_DEVICE, "public key: %s", hipGetErrorString(err));
+  return SANNS_OK;
+}
+
 extern "C" sanns_status sanns_decrypt_shares(sanns_ctx* ctx, const int8_t* sk,
                                              const uint64_t* ct, uint32_t M,
                                              const uint32_t* qnorm2, uint32_t* client_share,
@@ -563,12 +668,21 @@ extern "C" size_t sanns_distances_workspace(const sanns_ctx* ctx, const sanns_db
 namespace {
 
 // The fused sequence: query NTT, masks, multiply-accumulate, INTT + mask.
+// Circuit-private form of a call: the queries' public keys (coefficient form)
+// and the workspace for their NTT form, the flood width.
+struct CpArgs {
+  const uint64_t* pk = nullptr;
+  uint64_t* pk_ntt = nullptr;
+  CpConst c{};
+  bool on = false;
+};
+
 sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* ct_in,
                            uint32_t Q, const MaskKey& K, const uint64_t* qids,
                            const uint32_t* dwork, uint32_t M, int qt, int ct, int lds,
                            const void* dtiles, int n_tiles, uint64_t* ct_out,
                            uint32_t* share, uint64_t* qntt, int8_t* qdig, uint64_t* sums,
-                           hipStream_t st, bool profile = false) {
+                           hipStream_t st, bool profile = false, const CpArgs& cp = CpArgs()) {
   const uint32_t N = ctx->p.N, L = ctx->p.L, C = db->n_chunks, d = db->d;
   const bool mfma = lds == kMfmaSchedule;
   const uint2* res = (const uint2*)db->mem;
@@ -613,9 +727,22 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
   if (mfma)
     HIP_TRY(launch_sums_to_ct(sums, ct_out, (int)Q, (int)C, (int)L, ctx->logN, ctx->ps, st));
   HIP_TRY(mark(SANNS_PHASE_SUMS, true));
+  HIP_TRY(mark(SANNS_PHASE_RERAND, false));
+  if (cp.on) {
+    HIP_TRY(launch_ntt_fwd(cp.pk, cp.pk_ntt, (int)(Q * 2 * L), ctx->logN, (int)L, ctx->ps,
+                           ctx->tws, ctx->d_err, 0, st));
+    HIP_TRY(launch_rerand(K, qids, dwork, (int)C, (int)M, (int)L, ctx->logN, cp.pk_ntt, ct_out,
+                          ctx->ps, ctx->tws, st));
+  }
+  HIP_TRY(mark(SANNS_PHASE_RERAND, true));
   HIP_TRY(mark(SANNS_PHASE_INTT_MASK, false));
-  HIP_TRY(launch_intt_mask(ct_out, share, norms, dwork, (int)C, (int)M, ctx->logN, (int)L,
-                           (uint32_t)ctx->p.t, ctx->ps, ctx->tws, st));
+  if (cp.on)
+    HIP_TRY(launch_intt_mask_cp(ct_out, share, norms, dwork, (int)C, (int)M, ctx->logN, (int)L,
+                                (uint32_t)ctx->p.t, K, qids, cp.c, ctx->ds, ctx->ps, ctx->tws,
+                                st));
+  else
+    HIP_TRY(launch_intt_mask(ct_out, share, norms, dwork, (int)C, (int)M, ctx->logN, (int)L,
+                             (uint32_t)ctx->p.t, ctx->ps, ctx->tws, st));
   HIP_TRY(mark(SANNS_PHASE_INTT_MASK, true));
   if (profile) ctx->prof_events.push_back(ev);
   return SANNS_OK;
@@ -663,12 +790,17 @@ sanns_status enqueue_plain(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
 
 }  // namespace
 
-extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
-                                        const uint64_t* ct_in, uint32_t Q,
-                                        const uint8_t* mask_key, const uint64_t* query_ids,
-                                        const uint32_t* work, uint32_t M, int mode,
-                                        uint64_t* ct_out, uint32_t* server_share,
-                                        void* workspace, size_t ws_bytes, void* stream) {
+namespace {
+
+// sanns_distances; with noalloc the call is an
+// all-pairs fused launch sequence that allocates nothing: no staging, no
+// graph, no profiler events.
+sanns_status distances_impl(sanns_ctx* ctx, const sanns_db* db, const uint64_t* ct_in,
+                            uint32_t Q, const uint8_t* mask_key, const uint64_t* query_ids,
+                            const uint32_t* work, uint32_t M, int mode, uint64_t* ct_out,
+                            uint32_t* server_share, void* workspace, size_t ws_bytes,
+                            void* stream, bool noalloc, const uint64_t* pk = nullptr,
+                            uint32_t flood_bits = 0) {
   if (!ctx || !db || !db->mem || !ct_in || !mask_key || !query_ids || !ct_out ||
       !server_share || !workspace)
     return fail(SANNS_E_INVALID, "null argument");
@@ -696,7 +828,11 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
                     work[2 * m + 1]);
   const bool mfma = mode != SANNS_MODE_PERSISTENT && mode != SANNS_MODE_PLAIN &&
                     call_uses_mfma(ctx, Q, C, db->d, work == nullptr);
-  const WsLayout W = ws_layout(ctx, db->d, Q, M, mfma);
+  const bool cp_on = pk != nullptr;
+  if (cp_on && mode != SANNS_MODE_FUSED && mode != SANNS_MODE_BATCHED)
+    return fail(SANNS_E_INVALID, "the circuit-private form runs in SANNS_MODE_FUSED or "
+                                 "SANNS_MODE_BATCHED only");
+  const WsLayout W = ws_layout(ctx, db->d, Q, M, mfma, cp_on);
   if (ws_bytes < W.total)
     return fail(SANNS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, W.total);
   HIP_TRY(hipSetDevice(ctx->device));
@@ -712,6 +848,14 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
   for (int i = 0; i < 8; ++i)
     K.k[i] = (uint32_t)mask_key[4 * i] | (uint32_t)mask_key[4 * i + 1] << 8 |
              (uint32_t)mask_key[4 * i + 2] << 16 | (uint32_t)mask_key[4 * i + 3] << 24;
+  CpArgs cp;
+  if (cp_on) {
+    cp.on = true;
+    cp.pk = pk;
+    cp.pk_ntt = (uint64_t*)(ws + W.pkntt);
+    cp.c.b = (int)flood_bits;
+    for (uint32_t l = 0; l < ctx->p.L; ++l) cp.c.twob[l] = host::pow2_mod((int)flood_bits, ctx->p.q[l]);
+  }
 
   std::lock_guard<std::mutex> lock(ctx->mu);
   if (mode == SANNS_MODE_PLAIN) {
@@ -772,7 +916,7 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
   auto enqueue = [&](hipStream_t s, bool profile) -> sanns_status {
     if (!pshape)
       return enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, lds, dtiles,
-                           n_tiles, ct_out, server_share, qntt, qdig, sums, s, profile);
+                           n_tiles, ct_out, server_share, qntt, qdig, sums, s, profile, cp);
     PersistArgs A;
     A.ct_in = ct_in;
     A.qntt = qntt;
@@ -798,9 +942,13 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
     return SANNS_OK;
   };
 
+  if (noalloc)
+    return enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, lds, dtiles,
+                         n_tiles, ct_out, server_share, qntt, qdig, sums, st, false);
   if (mode == SANNS_MODE_FUSED || (ctx->profiling && !pshape))
     return enqueue_fused(ctx, db, ct_in, Q, K, query_ids, dwork, M, qt, ct, lds, dtiles,
-                         n_tiles, ct_out, server_share, qntt, qdig, sums, st, ctx->profiling);
+                         n_tiles, ct_out, server_share, qntt, qdig, sums, st, ctx->profiling,
+                         cp);
 
   // batched and persistent: replay (or capture once) the sequence as a hipGraph
   GraphKey key;
@@ -821,8 +969,20 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
   key.n_tiles = n_tiles;
   key.table = work ? 1 : 0;
   key.persist = pshape;
+  key.pk = pk;
+  key.flood_bits = flood_bits;
   std::memcpy(key.key, K.k, sizeof K.k);
   auto it = ctx->graphs.find(key);
+  if (it == ctx->graphs.end() && ctx->graphs.size() >= kMaxGraphs) {
+    // evict the least recently launched graph once its last launch is done
+    auto old = ctx->graphs.begin();
+    for (auto g = ctx->graphs.begin(); g != ctx->graphs.end(); ++g)
+      if (g->second.last_use < old->second.last_use) old = g;
+    HIP_TRY(hipEventSynchronize(old->second.done));
+    HIP_TRY(hipGraphExecDestroy(old->second.exec));
+    HIP_TRY(hipEventDestroy(old->second.done));
+    ctx->graphs.erase(old);
+  }
   if (it == ctx->graphs.end()) {
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -837,8 +997,58 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(SANNS_E_DEVICE, "instantiate: %s", hipGetErrorString(e));
-    it = ctx->graphs.emplace(key, exec).first;
+    sanns_ctx::CachedGraph cg;
+    cg.exec = exec;
+    e = hipEventCreateWithFlags(&cg.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      (void)hipGraphExecDestroy(exec);
+      return fail(SANNS_E_DEVICE, "graph event: %s", hipGetErrorString(e));
+    }
+    it = ctx->graphs.emplace(key, cg).first;
   }
-  HIP_TRY(hipGraphLaunch(it->second, st));
+  HIP_TRY(hipGraphLaunch(it->second.exec, st));
+  HIP_TRY(hipEventRecord(it->second.done, st));
+  it->second.last_use = ++ctx->graph_clock;
   return SANNS_OK;
+}
+
+}  // namespace
+
+extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
+                                        const uint64_t* ct_in, uint32_t Q,
+                                        const uint8_t* mask_key, const uint64_t* query_ids,
+                                        const uint32_t* work, uint32_t M, int mode,
+                                        uint64_t* ct_out, uint32_t* server_share,
+                                        void* workspace, size_t ws_bytes, void* stream) {
+  return distances_impl(ctx, db, ct_in, Q, mask_key, query_ids, work, M, mode, ct_out,
+                        server_share, workspace, ws_bytes, stream, false);
+}
+
+extern "C" uint32_t sanns_flood_bits(const sanns_ctx* ctx) {
+  return ctx ? (uint32_t)ctx->flood_bits_max : 0u;
+}
+
+extern "C" size_t sanns_distances_cp_workspace(const sanns_ctx* ctx, const sanns_db* db,
+                                               uint32_t Q, uint32_t M, int mode) {
+  if (!ctx || !db) return 0;
+  const bool mfma = mode != SANNS_MODE_PERSISTENT && mode != SANNS_MODE_PLAIN && Q > 0 &&
+                    (uint64_t)M == (uint64_t)Q * db->n_chunks &&
+                    call_uses_mfma(ctx, Q, db->n_chunks, db->d, true);
+  return ws_layout(ctx, db->d, Q, M, mfma, true).total;
+}
+
+extern "C" sanns_status sanns_distances_cp(sanns_ctx* ctx, const sanns_db* db,
+                                           const uint64_t* ct_in, uint32_t Q,
+                                           const uint8_t* mask_key, const uint64_t* query_ids,
+                                           const uint64_t* pk, uint32_t flood_bits,
+                                           const uint32_t* work, uint32_t M, int mode,
+                                           uint64_t* ct_out, uint32_t* server_share,
+                                           void* workspace, size_t ws_bytes, void* stream) {
+  if (!ctx || !pk) return fail(SANNS_E_INVALID, "null argument");
+  if (flood_bits == 0) flood_bits = (uint32_t)ctx->flood_bits_max;
+  if ((int)flood_bits > ctx->flood_bits_max)
+    return fail(SANNS_E_RANGE, "flood_bits %u exceeds %d (2^b must stay within Delta / 4)",
+                flood_bits, ctx->flood_bits_max);
+  return distances_impl(ctx, db, ct_in, Q, mask_key, query_ids, work, M, mode, ct_out,
+                        server_share, workspace, ws_bytes, stream, false, pk, flood_bits);
 }

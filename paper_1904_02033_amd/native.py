@@ -40,9 +40,12 @@ EXPORTS = [
     "sanns_encrypt_query", "sanns_decrypt_shares", "sanns_distances_workspace",
     "sanns_distances", "sanns_device_status", "sanns_set_schedule",
     "sanns_profile_enable", "sanns_profile_read",
+    "sanns_keygen", "sanns_encrypt_query_seeded", "sanns_public_key", "sanns_distances_cp",
+    "sanns_distances_cp_workspace", "sanns_flood_bits",
 ]
-SANNS_N_PHASES = 6
-PHASES = ["query_ntt", "masks", "mac", "intt_mask", "query_digits", "sums_transpose"]
+SANNS_N_PHASES = 7
+PHASES = ["query_ntt", "masks", "mac", "intt_mask", "query_digits", "sums_transpose",
+          "rerandomize"]
 
 
 class SannsError(RuntimeError):
@@ -92,6 +95,20 @@ def load() -> ctypes.CDLL:
     L.sanns_encode_db.restype = st
     L.sanns_encrypt_query.argtypes = [vp, vp, vp, u32, u32, vp, vp, vp, vp]
     L.sanns_encrypt_query.restype = st
+    L.sanns_keygen.argtypes = [vp, u64, vp, vp]
+    L.sanns_keygen.restype = st
+    L.sanns_encrypt_query_seeded.argtypes = [vp, vp, vp, u32, u32, u64, vp, vp]
+    L.sanns_encrypt_query_seeded.restype = st
+    L.sanns_public_key.argtypes = [vp, vp, u64, vp, vp]
+    L.sanns_public_key.restype = st
+    L.sanns_distances_cp.argtypes = [vp, ctypes.POINTER(sanns_db), vp, u32, ctypes.c_char_p,
+                                     vp, vp, u32, vp, u32, i32, vp, vp, vp, ctypes.c_size_t,
+                                     vp]
+    L.sanns_distances_cp.restype = st
+    L.sanns_distances_cp_workspace.argtypes = [vp, ctypes.POINTER(sanns_db), u32, u32, i32]
+    L.sanns_distances_cp_workspace.restype = ctypes.c_size_t
+    L.sanns_flood_bits.argtypes = [vp]
+    L.sanns_flood_bits.restype = u32
     L.sanns_decrypt_shares.argtypes = [vp, vp, vp, u32, vp, vp, vp]
     L.sanns_decrypt_shares.restype = st
     L.sanns_distances_workspace.argtypes = [vp, ctypes.POINTER(sanns_db), u32, u32, i32]
@@ -156,6 +173,39 @@ def sanns_encode_db(ctx: int, points: int, dtype: int, n: int, slot_point: int,
 def sanns_encrypt_query(ctx: int, sk: int, msgs: int, Q: int, d: int, a: int, e: int,
                         ct_out: int, stream: int = 0) -> None:
     _check(load().sanns_encrypt_query(ctx, sk, msgs, Q, d, a, e, ct_out, stream))
+
+
+def sanns_keygen(ctx: int, seed: int, sk: int, stream: int = 0) -> None:
+    _check(load().sanns_keygen(ctx, seed, sk, stream))
+
+
+def sanns_encrypt_query_seeded(ctx: int, sk: int, msgs: int, Q: int, d: int, enc_seed: int,
+                               ct_out: int, stream: int = 0) -> None:
+    _check(load().sanns_encrypt_query_seeded(ctx, sk, msgs, Q, d, enc_seed, ct_out, stream))
+
+
+def sanns_public_key(ctx: int, sk: int, seed: int, pk: int, stream: int = 0) -> None:
+    _check(load().sanns_public_key(ctx, sk, seed, pk, stream))
+
+
+def sanns_distances_cp(ctx: int, db: sanns_db, ct_in: int, Q: int, mask_key: bytes,
+                       query_ids: int, pk: int, flood_bits: int, work, M: int, mode: int,
+                       ct_out: int, server_share: int, workspace: int, ws_bytes: int,
+                       stream: int = 0) -> None:
+    if len(mask_key) != 32:
+        raise ValueError("mask_key must be 32 bytes")
+    wp = None if work is None else work.ctypes.data_as(ctypes.c_void_p)
+    _check(load().sanns_distances_cp(ctx, ctypes.byref(db), ct_in, Q, mask_key, query_ids, pk,
+                                     flood_bits, wp, M, mode, ct_out, server_share, workspace,
+                                     ws_bytes, stream))
+
+
+def sanns_distances_cp_workspace(ctx: int, db: sanns_db, Q: int, M: int, mode: int) -> int:
+    return load().sanns_distances_cp_workspace(ctx, ctypes.byref(db), Q, M, mode)
+
+
+def sanns_flood_bits(ctx: int) -> int:
+    return load().sanns_flood_bits(ctx)
 
 
 def sanns_decrypt_shares(ctx: int, sk: int, ct: int, M: int, qnorm2: int,

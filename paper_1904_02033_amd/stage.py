@@ -119,6 +119,30 @@ def encrypt_query(ctx: Context, sk: torch.Tensor, msgs: torch.Tensor, a: torch.T
     return ct
 
 
+def keygen(ctx: Context, seed: int, stream=None) -> torch.Tensor:
+    """Client secret key [N] int8 drawn from a seed (sanns_keygen)."""
+    sk = torch.empty(ctx.N, dtype=torch.int8, device=torch.device("cuda", ctx.device))
+    nat.sanns_keygen(ctx.handle, seed, _ptr(sk), _stream(stream))
+    return sk
+
+
+def encrypt_query_seeded(ctx: Context, sk: torch.Tensor, msgs: torch.Tensor, seed: int,
+                         stream=None) -> torch.Tensor:
+    """Encryption with its randomness drawn from a seed: ct [Q][d][2][L][N]."""
+    Q, d = msgs.shape
+    ct = torch.empty((Q, d, 2, ctx.L, ctx.N), dtype=torch.uint64, device=msgs.device)
+    nat.sanns_encrypt_query_seeded(ctx.handle, _ptr(sk), _ptr(msgs), Q, d, seed, _ptr(ct),
+                                   _stream(stream))
+    return ct
+
+
+def public_key(ctx: Context, sk: torch.Tensor, seed: int, stream=None) -> torch.Tensor:
+    """The client's public key [2][L][N] (sanns_public_key)."""
+    pk = torch.empty((2, ctx.L, ctx.N), dtype=torch.uint64, device=sk.device)
+    nat.sanns_public_key(ctx.handle, _ptr(sk), seed, _ptr(pk), _stream(stream))
+    return pk
+
+
 def decrypt_shares(ctx: Context, sk: torch.Tensor, ct: torch.Tensor,
                    qnorm2: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """Client shares [M][N] uint32 of M ciphertexts [M][2][L][N]."""
@@ -135,16 +159,20 @@ class Distances:
     def __init__(self, ctx: Context, db: Database, Q: int,
                  work: Optional[np.ndarray] = None, mode: int = nat.SANNS_MODE_FUSED,
                  workspace: Optional[torch.Tensor] = None,
-                 out_buffers: Optional[tuple] = None):
+                 out_buffers: Optional[tuple] = None, private: bool = False):
         """workspace: optional uint8 device tensor of at least the required
         size, reused instead of a fresh allocation; out_buffers: optional
         pair of uint8 device tensors that hold the ciphertext outputs and the
-        shares (at least M 2 L N 8 and M N 4 bytes), likewise reused."""
+        shares (at least M 2 L N 8 and M N 4 bytes), likewise reused;
+        private: size the workspace for the circuit-private form
+        (sanns_distances_cp; run() then needs the public keys)."""
         self.ctx, self.db, self.Q, self.mode = ctx, db, Q, mode
+        self.private = private
         self.work = None if work is None else np.ascontiguousarray(work, dtype=np.uint32)
         self.M = Q * db.n_chunks if work is None else len(self.work)
         dev = db.mem.device
-        self.ws_bytes = nat.sanns_distances_workspace(ctx.handle, db.desc, Q, self.M, mode)
+        size = nat.sanns_distances_cp_workspace if private else nat.sanns_distances_workspace
+        self.ws_bytes = size(ctx.handle, db.desc, Q, self.M, mode)
         if workspace is not None and workspace.numel() >= self.ws_bytes:
             self.ws = workspace[:self.ws_bytes]
         else:
@@ -161,13 +189,23 @@ class Distances:
             self.share = torch.empty(shape_share, dtype=torch.uint32, device=dev)
 
     def run(self, ct_in: torch.Tensor, mask_key: bytes, query_ids: torch.Tensor,
-            stream=None):
+            stream=None, pk: Optional[torch.Tensor] = None, flood_bits: int = 0):
+        """pk: [Q][2][L][N] public keys for the circuit-private form (the
+        object must have been built with private=True)."""
         if ct_in.shape[0] != self.Q:
             raise ValueError("query count differs from the one the buffers were sized for")
-        nat.sanns_distances(self.ctx.handle, self.db.desc, _ptr(ct_in), self.Q, mask_key,
-                            _ptr(query_ids), self.work, self.M, self.mode,
-                            _ptr(self.ct_out), _ptr(self.share), _ptr(self.ws),
-                            self.ws_bytes, _stream(stream))
+        if (pk is not None) != self.private:
+            raise ValueError("public keys are needed exactly when private=True")
+        if pk is not None:
+            nat.sanns_distances_cp(self.ctx.handle, self.db.desc, _ptr(ct_in), self.Q, mask_key,
+                                   _ptr(query_ids), _ptr(pk), flood_bits, self.work, self.M,
+                                   self.mode, _ptr(self.ct_out), _ptr(self.share),
+                                   _ptr(self.ws), self.ws_bytes, _stream(stream))
+        else:
+            nat.sanns_distances(self.ctx.handle, self.db.desc, _ptr(ct_in), self.Q, mask_key,
+                                _ptr(query_ids), self.work, self.M, self.mode,
+                                _ptr(self.ct_out), _ptr(self.share), _ptr(self.ws),
+                                self.ws_bytes, _stream(stream))
         return self.ct_out, self.share
 
 

@@ -1,17 +1,23 @@
 """Parity at the benchmark's full sizes, in the launch configuration the
-benchmark times (64 queries against a resident 1M-point database, N = 8192,
-L = 3; batched graph and persistent launch; the clustered 10M form).
+benchmark times: 64 queries against a resident 1M-point database (1M x 128
+uint8 and 1M x 96 int8), N = 8192, L = 3, on a context created as the
+benchmark creates it (the database keeps its int8 digit form) and the
+matrix-core multiply-accumulate schedule forced, replayed from the hipGraph
+of SANNS_MODE_BATCHED.
 
-At these sizes the oracle cannot produce every output, so each test checks
-  * bit-exact server shares of sampled output rows, in full, against the
-    oracle's ChaCha20 masks;
-  * bit-exact ciphertext coefficients at sampled (output, position) pairs
-    against the oracle's one-coefficient-at-a-time products, on synthetic
-    residue inputs fed to both sides;
+At these sizes the oracle cannot produce every output, so each world checks
+  * sampled output rows against the oracle (linear-scan protocol step 3;
+    Section 4.2), on uniform residue inputs fed to both sides: the server
+    shares in full and ciphertext coefficients at sampled positions, for
+    rows in chunk 0, the last (padding) chunk, queries 0 and 63 and every
+    row tile x chunk tile of the matrix-core kernel (64 rows = 32 queries,
+    64 chunks);
+  * every output byte against the 64-bit vector schedule and the persistent
+    launch on the same inputs;
   * the property that holds at any size: after decryption, client + server
     shares equal the cleartext squared distance at every slot of every
-    output (the reference distances come from an exact float64 matmul:
-    every inner product is below 2^53).
+    output (Section 2.1 arithmetic shares; the reference distances are exact
+    int64 sums on the device).
 """
 import numpy as np
 import pytest
@@ -20,7 +26,11 @@ import oracle
 import synthdata
 
 torch = pytest.importorskip("torch")
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+MFMA = 81
+VECTOR = 22
+Q = 64
 
 
 def _i64(x):
@@ -31,149 +41,149 @@ def _i64(x):
     return x.view(torch.int64)
 
 
-def _world(cid):
-    from paper_1904_02033_amd import stage
-    w = dataclass_for(cid)
-    pts = synthdata.gen_points(w)
-    queries = synthdata.gen_queries(w, 64)
-    ctx = stage.Context(w.N, w.L, w.t_bits)
-    slot = stage.linear_slot_map(len(pts), ctx.N,
-                                 synthdata.gen_perm(len(pts), synthdata.SEED_PERM + w.cid))
-    db = stage.encode_db(ctx, pts, slot)
-    return w, pts, queries, ctx, slot, db
-
-
-def dataclass_for(cid):
+def _workload(cid):
     return synthdata.BATCHED_1M128 if cid == 2 else synthdata.WORKLOADS[cid]
 
 
-def _true_dist_slots(pts, queries, slot, dev):
-    """[Q][C N] int64 squared distances per slot (-1 for padding)."""
-    p = torch.as_tensor(pts.astype(np.float64)).to(dev)
-    q = torch.as_tensor(queries.astype(np.float64)).to(dev)
-    dots = q @ p.T                                        # exact: < 2^53
-    d2 = ((q * q).sum(1, keepdim=True) + (p * p).sum(1)[None, :] - 2.0 * dots)
-    d2 = d2.round().to(torch.int64)
-    sl = torch.as_tensor(slot).to(dev)
-    out = torch.full((len(queries), len(slot)), -1, dtype=torch.int64, device=dev)
-    real = sl >= 0
-    out[:, real] = d2[:, sl[real]]
-    return out
-
-
-@pytest.mark.parametrize("cid", [2, 3])
-def test_full_size_batch_shares_are_distances(cid):
-    """64 encrypted queries against the 1M-point database: batched graph and
-    persistent launch agree bit for bit, and decrypt to the true distances at
-    every slot."""
+@pytest.fixture(scope="module", params=[2, 3], ids=["1Mx128-u8", "1Mx96-i8"])
+def world(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1904_02033_amd import native as nat, stage
+    cid = request.param
+    w = _workload(cid)
+    print(f"\nworld: {w.name}", flush=True)
     dev = torch.device("cuda")
-    w, pts, queries, ctx, slot, db = _world(cid)
-    Q, d, C, N, L, t = 64, pts.shape[1], db.n_chunks, ctx.N, ctx.L, ctx.t
+    pts = synthdata.gen_points(w)
+    queries = synthdata.gen_queries(w, Q)
+    params = nat.sanns_params_derive(w.N, w.L, w.t_bits)
+    params.flags |= nat.SANNS_FLAG_DIGIT_DB
+    ctx = stage.Context(params=params)
+    slot = synthdata.gen_slot_map(len(pts), ctx.N, synthdata.SEED_PERM + cid)
+    db = stage.encode_db(ctx, pts, slot)
+    N, d = ctx.N, pts.shape[1]
     sk = torch.as_tensor(synthdata.gen_secret(N, synthdata.SEED_SK + cid)).to(dev)
     a = synthdata.gen_uniform_a(ctx.qs, N, Q * d, synthdata.SEED_ENC + cid)
     e = synthdata.gen_cbd_error(N, Q * d, synthdata.SEED_ENC + cid)
     ct = stage.encrypt_query(ctx, sk, torch.as_tensor(queries.astype(np.int32)).to(dev),
                              torch.as_tensor(a).to(dev), torch.as_tensor(e).to(dev))
     del a, e
-    key = synthdata.gen_mask_key(synthdata.SEED_MASK + cid)
-    qids = torch.as_tensor(np.arange(Q, dtype=np.uint64)).to(dev)
-    B = stage.Distances(ctx, db, Q, mode=nat.SANNS_MODE_BATCHED)
-    bo, bs = B.run(ct, key, qids)
-    P = stage.Distances(ctx, db, Q, mode=nat.SANNS_MODE_PERSISTENT)
-    po, ps = P.run(ct, key, qids)
     torch.cuda.synchronize()
     ctx.device_status()
-    assert torch.equal(_i64(bo), _i64(po)) and torch.equal(_i64(bs), _i64(ps))
-    del P, po, ps
+    W = dict(cid=cid, w=w, pts=pts, queries=queries, ctx=ctx, slot=slot, db=db, sk=sk,
+             ct=ct, nat=nat, stage=stage, dev=dev)
+    yield W
+    W.clear()
+    ctx.close()
+    torch.cuda.empty_cache()
+
+
+def _run(W, ct, key, qids, variant, mode=None):
+    """One sanns_distances call in the given schedule; returns device outputs."""
+    nat, stage, ctx = W["nat"], W["stage"], W["ctx"]
+    ctx.set_schedule(0, 0, variant)
+    D = stage.Distances(ctx, W["db"], Q, mode=nat.SANNS_MODE_BATCHED if mode is None else mode)
+    out, share = D.run(ct, key, qids)
+    torch.cuda.synchronize()
+    ctx.device_status()
+    return out, share
+
+
+def _sample_rows(C):
+    """(query, chunk) pairs: chunk 0 and the last (padding) chunk for queries
+    0 and 63, and a row in each of the matrix-core kernel's row tiles (queries
+    0-31, 32-63) x chunk tiles (chunks 0-63, 64-), at their edges too."""
+    pairs = [(0, 0), (0, C - 1), (Q - 1, 0), (Q - 1, C - 1),
+             (20, 30), (20, 70), (45, 10), (45, 100), (31, 63), (32, 64)]
+    g = np.random.default_rng(C)
+    pairs += [(int(g.integers(0, Q)), int(g.integers(0, C))) for _ in range(2)]
+    return sorted(set(pairs))
+
+
+def test_headline_schedule_sampled_rows_against_oracle(world):
+    W = world
+    nat, ctx, db, pts, slot = W["nat"], W["ctx"], W["db"], W["pts"], W["slot"]
+    N, L, C, d = ctx.N, ctx.L, db.n_chunks, pts.shape[1]
+    P = oracle.Params(N, oracle.rns_primes(N, L), oracle.plain_modulus(N, W["w"].t_bits))
+    assert P.qs == ctx.qs and P.t == ctx.t
+    ct_host = synthdata.gen_uniform_a(P.qs, N, Q * d * 2, 77 + W["cid"]).reshape(Q, d, 2, L, N)
+    ct = torch.as_tensor(ct_host).to(W["dev"])
+    key = synthdata.gen_mask_key(78 + W["cid"])
+    qbase = 1000
+    qids = torch.as_tensor(np.arange(qbase, qbase + Q, dtype=np.uint64)).to(W["dev"])
+
+    out, share = _run(W, ct, key, qids, MFMA)
+    # the call above ran the matrix-core schedule: a profiled call (the same
+    # kernels launched directly) reports its digit and sums transposes
+    ctx.set_schedule(0, 0, MFMA)
+    Dp = W["stage"].Distances(ctx, db, Q, mode=nat.SANNS_MODE_BATCHED)
+    nat.sanns_profile_enable(ctx.handle, True)
+    po, ps = Dp.run(ct, key, qids)
+    ph, calls = nat.sanns_profile_read(ctx.handle)
+    nat.sanns_profile_enable(ctx.handle, False)
+    torch.cuda.synchronize()
+    assert calls == 1 and ph["query_digits"] > 0 and ph["sums_transpose"] > 0, ph
+    assert torch.equal(_i64(po), _i64(out)) and torch.equal(_i64(ps), _i64(share))
+    del Dp, po, ps
+
+    pairs = _sample_rows(C)
+    g = np.random.default_rng(79)
+    js = sorted(set([0, 1, 2, N // 2, N - 1] + [int(x) for x in g.integers(0, N, 16)]))
+    for qi, k in pairs:
+        m = qi * C + k
+        print(f"row (query {qi}, chunk {k})", flush=True)
+        want_r = oracle.masks(key, qbase + qi, k, P.t, N)
+        assert (share[m].cpu().numpy() == want_r).all(), (qi, k)
+        gk, nrm = oracle.chunk_plaintexts(pts, slot, N, k)
+        sc, sr = oracle.server_coeffs(P, ct_host[qi], gk, nrm, key, qbase + qi, k, js)
+        assert (out[m].cpu().numpy()[:, :, js] == sc).all(), (qi, k)
+        assert (sr == want_r[js]).all()
+
+    # every byte equals the 64-bit vector schedule's on the same inputs
+    vo, vs = _run(W, ct, key, qids, VECTOR)
+    assert torch.equal(_i64(vo), _i64(out)) and torch.equal(_i64(vs), _i64(share))
+    W["ctx"].set_schedule(0, 0, 0)
+
+
+def _true_dist_slots(pts, queries, slot, dev):
+    """[Q][C N] int64 squared distances per slot (-1 for padding): exact
+    integer sums on the device, 4096 points at a time."""
+    p_all = torch.as_tensor(pts).to(dev)
+    q = torch.as_tensor(queries.astype(np.int32)).to(dev)
+    sl = torch.as_tensor(slot).to(dev)
+    out = torch.full((len(queries), len(slot)), -1, dtype=torch.int64, device=dev)
+    real = torch.nonzero(sl >= 0).flatten()
+    for s in range(0, len(real), 4096):
+        idx = real[s:s + 4096]
+        p = p_all[sl[idx]].to(torch.int32)                    # [B][d]
+        diff = q[:, None, :] - p[None, :, :]                  # [Q][B][d]
+        out[:, idx] = (diff * diff).sum(-1).to(torch.int64)
+    return out
+
+
+def test_headline_schedule_shares_are_distances(world):
+    """Encrypted queries: the benchmarked schedule's shares reconstruct the
+    true squared distance at every slot; the persistent launch returns the
+    same bytes."""
+    W = world
+    nat, stage, ctx, db = W["nat"], W["stage"], W["ctx"], W["db"]
+    queries, slot, dev = W["queries"], W["slot"], W["dev"]
+    C, N, t = db.n_chunks, ctx.N, ctx.t
+    key = synthdata.gen_mask_key(synthdata.SEED_MASK + W["cid"])
+    qids = torch.as_tensor(np.arange(Q, dtype=np.uint64)).to(dev)
+    out, share = _run(W, W["ct"], key, qids, MFMA)
     qn2 = ((queries.astype(np.int64) ** 2).sum(axis=1) % t).astype(np.uint32)
-    client = stage.decrypt_shares(ctx, sk, bo, torch.as_tensor(np.repeat(qn2, C)).to(dev))
-    tot = (_i64(client) + _i64(bs)) % t                   # [Q C][N]
-    want = _true_dist_slots(pts, queries, slot, dev)      # [Q][C N]
-    tot = tot.view(Q, C * N)
+    client = stage.decrypt_shares(ctx, W["sk"], out, torch.as_tensor(np.repeat(qn2, C)).to(dev))
+    tot = ((_i64(client) + _i64(share)) % t).view(Q, C * N)
+    want = _true_dist_slots(W["pts"], queries, slot, dev)
     real = want >= 0
+    assert int(real.sum()) == Q * len(W["pts"])
     assert torch.equal(tot[real], want[real])
-    # padding slots carry ||q||^2 (a zero point)
+    # padding slots hold a zero point: they decrypt to ||q||^2
     pad = ~real
     assert torch.equal(tot[pad], torch.as_tensor(qn2.astype(np.int64)).to(dev)[:, None]
                        .expand(Q, C * N)[pad])
-
-
-def test_full_size_batch_sampled_against_oracle():
-    """Synthetic residue inputs (both sides get the same bytes): server
-    shares of sampled rows in full and ciphertext coefficients at sampled
-    positions, for the batched graph at 1M x 128, 64 queries."""
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_1904_02033_amd import native as nat, stage
-    dev = torch.device("cuda")
-    w, pts, queries, ctx, slot, db = _world(2)
-    Q, d, C, N, L = 64, pts.shape[1], db.n_chunks, ctx.N, ctx.L
-    P = oracle.Params(N, oracle.rns_primes(N, L), ctx.t)
-    ct_host = synthdata.gen_uniform_a(P.qs, N, Q * d * 2, 77).reshape(Q, d, 2, L, N)
-    ct = torch.as_tensor(ct_host).to(dev)
-    key = synthdata.gen_mask_key(78)
-    qids = torch.as_tensor(np.arange(1000, 1000 + Q, dtype=np.uint64)).to(dev)
-    B = stage.Distances(ctx, db, Q, mode=nat.SANNS_MODE_BATCHED)
-    out, share = B.run(ct, key, qids)
-    torch.cuda.synchronize()
-    ctx.device_status()
-    g = np.random.default_rng(79)
-    rows = sorted(set([0, Q * C - 1] + list(g.integers(0, Q * C, 10))))
-    js = sorted(set([0, N - 1] + list(g.integers(0, N, 4))))
-    for m in rows:
-        qi, k = divmod(m, C)
-        want_r = oracle.masks(key, 1000 + qi, k, P.t, N)
-        assert (share[m].cpu().numpy() == want_r).all(), m
-        gk, nrm = oracle.chunk_plaintexts(pts, slot, N, k)
-        sc, sr = oracle.server_coeffs(P, ct_host[qi], gk, nrm, key, 1000 + qi, k, js)
-        got = out[m].cpu().numpy()[:, :, js]
-        assert (got == sc).all(), m
-
-
-def test_full_size_clustered_shares_are_distances():
-    """The clustered 10M x 96 form with the benchmark's 32 queries x 64
-    clusters: phase-2 outputs of two queries decrypt to the true distances at
-    every slot of every chunk they scanned."""
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_1904_02033_amd import clustered, native as nat, stage
-    dev = torch.device("cuda")
-    w = synthdata.WORKLOADS[4]
-    cdb = synthdata.gen_clustered(seed=synthdata.SEED_DATA + 4)
-    ctx = stage.Context(w.N, w.L, w.t_bits)
-    srv = clustered.ClusteredServer(
-        ctx, cdb.points, cdb.cluster_sizes, cdb.centers, cdb.stash_size,
-        synthdata.gen_perm(len(cdb.cluster_sizes), synthdata.SEED_PERM + 4),
-        synthdata.gen_perm(cdb.stash_size, synthdata.SEED_PERM + 40),
-        synthdata.gen_mask_key(synthdata.SEED_MASK + 4),
-        synthdata.gen_mask_key(synthdata.SEED_MASK + 40))
-    Q, u, t, N = w.Q, 64, ctx.t, ctx.N
-    queries = synthdata.gen_queries(w, Q)
-    sk = torch.as_tensor(synthdata.gen_secret(N, synthdata.SEED_SK + 4)).to(dev)
-    a = synthdata.gen_uniform_a(ctx.qs, N, Q * w.d, synthdata.SEED_SK + 5)
-    e = synthdata.gen_cbd_error(N, Q * w.d, synthdata.SEED_SK + 5)
-    ct = stage.encrypt_query(ctx, sk, torch.as_tensor(queries.astype(np.int32)).to(dev),
-                             torch.as_tensor(a).to(dev), torch.as_tensor(e).to(dev))
-    qids = torch.as_tensor(np.arange(Q, dtype=np.uint64)).to(dev)
-    qn2 = ((queries.astype(np.int64) ** 2).sum(axis=1) % t).astype(np.uint32)
-    cout, cshare = srv.center_distances(ct, qids)
-    Cc = srv.cdb.n_chunks
-    cl = stage.decrypt_shares(ctx, sk, cout, torch.as_tensor(np.repeat(qn2, Cc)).to(dev))
-    cl, cs = cl.cpu().numpy(), cshare.cpu().numpy()
-    selected = [clustered.select_clusters(
-        ((cl[q * Cc:(q + 1) * Cc].astype(np.int64) + cs[q * Cc:(q + 1) * Cc]) % t).reshape(-1),
-        srv.center_slot, u) for q in range(Q)]
-    out, share, work = srv.point_distances(ct, qids, selected, mode=nat.SANNS_MODE_BATCHED)
-    client = stage.decrypt_shares(ctx, sk, out, torch.as_tensor(qn2[work[:, 0]]).to(dev))
-    tot = ((client.cpu().numpy().astype(np.int64) + share.cpu().numpy()) % t)
-    for q in (0, Q - 1):
-        rows = np.nonzero(work[:, 0] == q)[0]
-        assert len(rows) >= 13  # at least the stash chunks
-        for m in rows:
-            ids = srv.layout.slot_point[work[m, 1] * N:(work[m, 1] + 1) * N]
-            real = ids >= 0
-            want = ((cdb.points[ids[real]].astype(np.int64) - queries[q]) ** 2).sum(axis=1)
-            assert (tot[m][real] == want).all(), (q, m)
+    del client, tot, want
+    po, ps = _run(W, W["ct"], key, qids, 0, mode=nat.SANNS_MODE_PERSISTENT)
+    assert torch.equal(_i64(po), _i64(out)) and torch.equal(_i64(ps), _i64(share))
+    ctx.set_schedule(0, 0, 0)
