@@ -343,6 +343,30 @@ size_t sanns_distances_cp_workspace(const sanns_ctx *ctx, const sanns_db *db,
  * Delta = floor(q / t) (0 for a null context). */
 uint32_t sanns_flood_bits(const sanns_ctx *ctx);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation: the fused
+ * form of sanns_distances for Q queries against every chunk of `db`
+ * (work == NULL, M = Q * n_chunks), with the workspace taken from a scratch
+ * array the library holds on each GPU (SANNS_NOALLOC_SCRATCH_BYTES, 64 MiB,
+ * kept until the process ends; its device address is looked up when a
+ * context is created on that GPU).  Arguments and outputs are those of
+ * sanns_distances; the outputs are bit-identical to it.  The call allocates
+ * nothing (no device or pinned memory, no graph, no profiler events; the
+ * per-phase profiler does not record it).  A call whose workspace would
+ * exceed the scratch array is rejected with SANNS_E_WORKSPACE: at N = 8192,
+ * L = 3 against a 123-chunk (1M-point) database that admits one query of up
+ * to 169 coordinates (the 1M x 128 scan of one query needs 48.4 MiB).  All calls on one GPU share its scratch array and every
+ * call leaves its contents behind: calls that overlap on one GPU (different
+ * streams or host threads) race and give undefined outputs; calls on one
+ * stream are ordered and safe.  Errors: those of sanns_distances. */
+#define SANNS_NOALLOC_SCRATCH_BYTES (64u << 20)
+sanns_status sanns_distances_noalloc(sanns_ctx *ctx, const sanns_db *db,
+                                     const uint64_t *ct_in, uint32_t Q,
+                                     const uint8_t *mask_key,
+                                     const uint64_t *query_ids,
+                                     uint64_t *ct_out, uint32_t *server_share,
+                                     void *stream);
+
 /* Synchronise `stream` and return (and clear) the context's device error
  * word: SANNS_E_RANGE if, since the last call, an input residue was >= q_l
  * or a slot index of sanns_encode_db was outside [-1, n) (such a slot is

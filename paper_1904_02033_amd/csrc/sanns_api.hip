@@ -18,10 +18,34 @@
 
 using namespace sanns;
 
+// Device scratch of sanns_distances_noalloc: one copy per GPU, held until the
+// process ends.  Host code never uses the name as an address; each device's
+// copy is located once with hipGetSymbolAddress (scratch_for_device).
+static __device__ __align__(256) unsigned char scratch[SANNS_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_last_error;
 
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current; looked up
+// on the first call for each device.
+hipError_t scratch_for_device(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
 
 sanns_status fail(sanns_status s, const char* fmt, ...) {
   char buf[512];
@@ -72,6 +96,7 @@ struct sanns_ctx {
   uint64_t tone = 0;  // floor(2^64 / t)
   uint64_t* d_tw = nullptr;
   uint32_t* d_err = nullptr;
+  void* scratch = nullptr;  // this device's copy of `scratch` (sanns_distances_noalloc)
   int flood_bits_max = 0;   // largest b with 2^b <= Delta / 4 (circuit-private form)
   hipStream_t cap_stream = nullptr;
   std::mutex mu;
@@ -397,6 +422,11 @@ extern "C" sanns_status sanns_ctx_create(const sanns_params* p, int device, sann
   }
   for (uint32_t l = 0; l < L; ++l)
     ctx->tws.tw[l] = reinterpret_cast<const u64x2*>(ctx->d_tw + (size_t)l * 6 * N);
+  e = scratch_for_device(device, &ctx->scratch);
+  if (e != hipSuccess) {
+    sanns_ctx_destroy(ctx);
+    return fail(SANNS_E_DEVICE, "scratch address: %s", hipGetErrorString(e));
+  }
   *out = ctx;
   return SANNS_OK;
 }
@@ -792,7 +822,7 @@ sanns_status enqueue_plain(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
 
 namespace {
 
-// sanns_distances; with noalloc the call is an
+// sanns_distances; with noalloc (sanns_distances_noalloc) the call is an
 // all-pairs fused launch sequence that allocates nothing: no staging, no
 // graph, no profiler events.
 sanns_status distances_impl(sanns_ctx* ctx, const sanns_db* db, const uint64_t* ct_in,
@@ -1051,4 +1081,24 @@ extern "C" sanns_status sanns_distances_cp(sanns_ctx* ctx, const sanns_db* db,
                 flood_bits, ctx->flood_bits_max);
   return distances_impl(ctx, db, ct_in, Q, mask_key, query_ids, work, M, mode, ct_out,
                         server_share, workspace, ws_bytes, stream, false, pk, flood_bits);
+}
+
+extern "C" sanns_status sanns_distances_noalloc(sanns_ctx* ctx, const sanns_db* db,
+                                                const uint64_t* ct_in, uint32_t Q,
+                                                const uint8_t* mask_key,
+                                                const uint64_t* query_ids, uint64_t* ct_out,
+                                                uint32_t* server_share, void* stream) {
+  if (!ctx || !db) return fail(SANNS_E_INVALID, "null argument");
+  if (!ctx->scratch) return fail(SANNS_E_DEVICE, "no scratch address for device %d", ctx->device);
+  const uint64_t M = (uint64_t)Q * db->n_chunks;
+  if (M > 0xFFFFFFFFull) return fail(SANNS_E_INVALID, "Q * n_chunks overflows");
+  const size_t need = sanns_distances_workspace(ctx, db, Q, (uint32_t)M, SANNS_MODE_FUSED);
+  if (need > (size_t)SANNS_NOALLOC_SCRATCH_BYTES)
+    return fail(SANNS_E_WORKSPACE,
+                "the call needs %zu bytes of scratch, more than the %u bytes the library holds "
+                "per device (SANNS_NOALLOC_SCRATCH_BYTES); use sanns_distances with a workspace",
+                need, (unsigned)SANNS_NOALLOC_SCRATCH_BYTES);
+  return distances_impl(ctx, db, ct_in, Q, mask_key, query_ids, nullptr, (uint32_t)M,
+                        SANNS_MODE_FUSED, ct_out, server_share, ctx->scratch,
+                        (size_t)SANNS_NOALLOC_SCRATCH_BYTES, stream, true);
 }

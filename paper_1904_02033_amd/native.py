@@ -39,10 +39,11 @@ EXPORTS = [
     "sanns_last_error", "sanns_ctx_params", "sanns_db_bytes", "sanns_encode_db",
     "sanns_encrypt_query", "sanns_decrypt_shares", "sanns_distances_workspace",
     "sanns_distances", "sanns_device_status", "sanns_set_schedule",
-    "sanns_profile_enable", "sanns_profile_read",
+    "sanns_profile_enable", "sanns_profile_read", "sanns_distances_noalloc",
     "sanns_keygen", "sanns_encrypt_query_seeded", "sanns_public_key", "sanns_distances_cp",
     "sanns_distances_cp_workspace", "sanns_flood_bits",
 ]
+SANNS_NOALLOC_SCRATCH_BYTES = 64 << 20
 SANNS_N_PHASES = 7
 PHASES = ["query_ntt", "masks", "mac", "intt_mask", "query_digits", "sums_transpose",
           "rerandomize"]
@@ -116,6 +117,9 @@ def load() -> ctypes.CDLL:
     L.sanns_distances.argtypes = [vp, ctypes.POINTER(sanns_db), vp, u32, ctypes.c_char_p,
                                   vp, vp, u32, i32, vp, vp, vp, ctypes.c_size_t, vp]
     L.sanns_distances.restype = st
+    L.sanns_distances_noalloc.argtypes = [vp, ctypes.POINTER(sanns_db), vp, u32,
+                                          ctypes.c_char_p, vp, vp, vp, vp]
+    L.sanns_distances_noalloc.restype = st
     L.sanns_device_status.argtypes = [vp, vp]
     L.sanns_device_status.restype = st
     L.sanns_set_schedule.argtypes = [vp, i32, i32, i32]
@@ -211,6 +215,15 @@ def sanns_flood_bits(ctx: int) -> int:
 def sanns_decrypt_shares(ctx: int, sk: int, ct: int, M: int, qnorm2: int,
                          client_share: int, stream: int = 0) -> None:
     _check(load().sanns_decrypt_shares(ctx, sk, ct, M, qnorm2, client_share, stream))
+
+
+def sanns_distances_noalloc(ctx: int, db: sanns_db, ct_in: int, Q: int, mask_key: bytes,
+                            query_ids: int, ct_out: int, server_share: int,
+                            stream: int = 0) -> None:
+    if len(mask_key) != 32:
+        raise ValueError("mask_key must be 32 bytes")
+    _check(load().sanns_distances_noalloc(ctx, ctypes.byref(db), ct_in, Q, mask_key,
+                                          query_ids, ct_out, server_share, stream))
 
 
 def sanns_distances_workspace(ctx: int, db: sanns_db, Q: int, M: int, mode: int) -> int:
