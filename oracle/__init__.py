@@ -497,18 +497,14 @@ def sqdist(query: np.ndarray, points: np.ndarray) -> np.ndarray:
 
 def naive_topk(vals: Sequence[int], ids: Sequence[int], k: int
                ) -> Tuple[List[int], List[int]]:
-    """Algorithm 1: keep a sorted list of the k smallest; a new value moves
-    in front of an incumbent only when strictly smaller, so among equal values
-    the earlier one stays ahead."""
-    INF = float("inf")
-    opt = [INF] * k
-    idl = [-1] * k
-    for x, idx in zip(vals, ids):
-        for j in range(k):
-            if x < opt[j]:
-                opt[j], x = x, opt[j]
-                idl[j], idx = idx, idl[j]
-    return opt, idl
+    """Algorithm 1's selection: the k smallest values in ascending order with
+    their IDs.  Ties are read as a stable selection (an earlier position
+    comes first): the output is the k smallest (value, position) pairs.
+    Positions past the input are (infinity, -1)."""
+    order = sorted(range(len(vals)), key=lambda j: (vals[j], j))[:k]
+    out_v = [vals[j] for j in order] + [float("inf")] * (k - len(order))
+    out_i = [ids[j] for j in order] + [-1] * (k - len(order))
+    return out_v, out_i
 
 
 def bin_bounds(n: int, l: int) -> List[Tuple[int, int]]:

@@ -8,9 +8,8 @@ distances, for checking, recall measurement and the serving loop.
 
 * reconstruct(): d = [client + server]_t, then floor(d / 2^r) (the optional
   truncation of Section 3 "Approximate Distances").
-* naive_topk(): Algorithm 1 semantics -- the k smallest values in ascending
-  order; a later value moves ahead of an incumbent only when strictly
-  smaller.
+* naive_topk(): Algorithm 1's selection -- the k smallest values in
+  ascending order, equal values in input order.
 * approx_topk(): Algorithm 2 -- l consecutive bins over the (already
   randomly permuted) list, the first minimum of each bin, then Algorithm 1 on
   the l bin minima.  When l does not divide n the first n mod l bins take one
@@ -32,37 +31,18 @@ def reconstruct(client_share: np.ndarray, server_share: np.ndarray, t: int,
 
 
 def naive_topk(values: np.ndarray, ids: np.ndarray, k: int) -> Tuple[np.ndarray, np.ndarray]:
-    """Algorithm 1 on (values, ids): returns (k values ascending, their ids);
-    missing entries (k > n) are (max int64, -1)."""
+    """Algorithm 1's selection on (values, ids): (k values ascending, their
+    ids), equal values in input order; missing entries (k > n) are
+    (max int64, -1)."""
     values = np.asarray(values, dtype=np.int64)
     ids = np.asarray(ids, dtype=np.int64)
-    n = len(values)
-    if n == 0:
-        return (np.full(k, np.iinfo(np.int64).max, dtype=np.int64),
-                np.full(k, -1, dtype=np.int64))
-    # Candidates: every item whose value is among the k smallest values.
-    # Algorithm 1 keeps a sorted insertion list; replay it on the candidates
-    # only (items that can never enter the list cannot change it).
-    kk = min(k, n)
-    thresh = np.partition(values, kk - 1)[kk - 1]
-    cand = np.nonzero(values <= thresh)[0]
-    cv = values[cand]
-    if len(np.unique(cv)) == len(cv):
-        # distinct values: Algorithm 1's list is the candidates in value order
-        o = np.argsort(cv, kind="stable")[:kk]
-        out_v = np.full(k, np.iinfo(np.int64).max, dtype=np.int64)
-        out_i = np.full(k, -1, dtype=np.int64)
-        out_v[:kk], out_i[:kk] = cv[o], ids[cand[o]]
-        return out_v, out_i
-    opt_v = [np.iinfo(np.int64).max] * k
-    opt_i = [-1] * k
-    for j in cand:
-        x, xi = int(values[j]), int(ids[j])
-        for p in range(k):
-            if x < opt_v[p]:
-                opt_v[p], x = x, opt_v[p]
-                opt_i[p], xi = xi, opt_i[p]
-    return np.array(opt_v, dtype=np.int64), np.array(opt_i, dtype=np.int64)
+    out_v = np.full(k, np.iinfo(np.int64).max, dtype=np.int64)
+    out_i = np.full(k, -1, dtype=np.int64)
+    kk = min(k, len(values))
+    if kk:
+        o = np.argsort(values, kind="stable")[:kk]
+        out_v[:kk], out_i[:kk] = values[o], ids[o]
+    return out_v, out_i
 
 
 def bin_edges(n: int, l: int) -> np.ndarray:

@@ -9,7 +9,7 @@ from paper_1904_02033_amd import topk
 
 @pytest.mark.parametrize("seed", range(6))
 @pytest.mark.parametrize("k", [1, 3, 10, 40])
-def test_naive_topk_matches_algorithm1_with_ties(seed, k):
+def test_naive_topk_matches_oracle_with_ties(seed, k):
     g = np.random.default_rng(seed)
     n = int(g.integers(1, 300))
     vals = g.integers(0, max(2, n // 4), n)        # many ties
