@@ -370,6 +370,25 @@ def chunk_plaintexts(points: np.ndarray, slot_pt: np.ndarray, N: int,
     return g, nrm
 
 
+def chunk_plaintexts_shares(shares: np.ndarray, norm_shares: np.ndarray, slot_pt: np.ndarray,
+                            N: int, k: int, t: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Plaintexts of chunk k when the server holds only additive shares p_s
+    (mod t) of the points and of their squared norms (Section 4.2, last
+    paragraph): g_{i,k}[j] = the representative of -2 p_s[i] mod t in
+    (-t/2, t/2] (0 for padding) and the norm plane = the norm share."""
+    ids = slot_pt[k * N:(k + 1) * N]
+    d = shares.shape[1]
+    g = np.zeros((d, N), dtype=np.int64)
+    nrm = np.zeros(N, dtype=np.int64)
+    real = ids >= 0
+    ps = shares[ids[real]].astype(np.int64)
+    v = (-2 * ps) % t
+    v = np.where(v > t // 2, v - t, v)
+    g[:, real] = v.T
+    nrm[real] = norm_shares[ids[real]].astype(np.int64)
+    return g, nrm
+
+
 def masks(key: bytes, query_id: int, chunk: int, t: int, N: int,
           j0: int = 0, cnt: int = None) -> np.ndarray:
     cnt = N - j0 if cnt is None else cnt

@@ -628,3 +628,45 @@ def test_flooding_too_wide_breaks_decryption():
     bad = sum(oracle.decrypt(P, oracle.rerandomize(P, f, pk, key, 5, k, b + 3), s)
               != oracle.decrypt(P, f, s) for k in range(4))
     assert bad >= 1
+
+
+# ---------------------------------------------------------------- secret-shared points
+
+def test_distances_on_secret_shared_points():
+    """Points and norms held as additive shares p = p_c + p_s (mod t)
+    (Section 4.2, last paragraph): the server's stage on its shares (full-range
+    plaintexts) plus the client's cleartext terms -2 <q, p_c> + ||p||^2_c give
+    [client + server]_t = ||q - p||^2 at every slot; the noise of the
+    full-range product obeys d N eta max|g| + (q mod t)(d max|g| + 2) < Delta/2
+    with max|g| = t / 2, and also at the workloads' parameters."""
+    P, pts, qv, s, ct, slot, key = _small_stage(n=40, d=5, N=16, L=2, t_bits=20)
+    g0 = np.random.default_rng(12)
+    n, d = pts.shape
+    pc = g0.integers(0, P.t, (n, d)).astype(np.int64)
+    psh = (pts.astype(np.int64) - pc) % P.t
+    nrm = (pts.astype(np.int64) ** 2).sum(axis=1)
+    nc = g0.integers(0, P.t, n).astype(np.int64)
+    nsh = (nrm - nc) % P.t
+    q64 = qv.astype(np.int64)
+    qn2 = int((q64 ** 2).sum()) % P.t
+    bound = d * P.N * 21 * (P.t // 2) + (P.q % P.t) * (d * (P.t // 2) + 2)
+    assert bound < P.delta // 2
+    for k in range(len(slot) // P.N):
+        g, nr = oracle.chunk_plaintexts_shares(psh, nsh, slot, P.N, k, P.t)
+        assert np.abs(g).max() <= P.t // 2
+        out, r = oracle.server_chunk(P, ct, g, nr, key, 9, k)
+        dec = oracle.decrypt(P, out, s)
+        ids = slot[k * P.N:(k + 1) * P.N]
+        V = [(-2 * int(psh[i] @ q64) + int(nsh[i]) if i >= 0 else 0) for i in ids]
+        msg = [(V[j] - int(r[j])) % P.t for j in range(P.N)]
+        assert dec == msg
+        assert max(abs(x) for x in oracle.noise(P, out, s, msg)) <= bound
+        for j, i in enumerate(ids):
+            if i < 0:
+                continue
+            client = (dec[j] + qn2 - 2 * int(pc[i] @ q64) + int(nc[i])) % P.t
+            assert (client + int(r[j])) % P.t == int(((pts[i].astype(np.int64) - q64) ** 2).sum())
+    for w in (synthdata.WORKLOADS[2], synthdata.WORKLOADS[3]):
+        Pw = oracle.Params.for_workload(w.N, w.L, w.t_bits)
+        bw = w.d * Pw.N * 21 * (Pw.t // 2) + (Pw.q % Pw.t) * (w.d * (Pw.t // 2) + 2)
+        assert bw < Pw.delta // 2 - Pw.t
