@@ -77,9 +77,12 @@ typedef struct {
     uint32_t flags;
 } sanns_params;
 
-/* Point coordinate types accepted by sanns_encode_db. */
+/* Point coordinate types accepted by sanns_encode_db (and by
+ * sanns_distances_gathered, which also takes SANNS_SHARE32). */
 #define SANNS_U8 0
 #define SANNS_I8 1
+#define SANNS_SHARE32 2 /* uint32 additive shares in [0, t) of secret-shared
+                           points (sanns_distances_gathered only)           */
 
 /* Execution forms of sanns_distances. */
 #define SANNS_MODE_PLAIN 0   /* one kernel launch per ciphertext operation    */
@@ -301,6 +304,93 @@ sanns_status sanns_distances(sanns_ctx *ctx, const sanns_db *db,
                              uint64_t *ct_out, uint32_t *server_share,
                              void *workspace, size_t ws_bytes, void *stream);
 
+/* The distance stage on chunks gathered for this call instead of a resident
+ * database (clustering-based protocol, steps 6-7: the points of each query's
+ * retrieved clusters; Section 4.2, last paragraph: when the points are
+ * secret-shared between client and server, the server's plaintexts are its
+ * shares).  Chunk m of the call holds in slot j the point
+ * slot_point[m N + j] (-1: padding) and belongs to query row_query[m]; it is
+ * encoded on the fly (as sanns_encode_db would, into the workspace) and
+ *   ct_out[m]       = sum_i c_{q,i} * g_{i,m}  +  Delta [ P_m - r ]_t
+ *   server_share[m] = r,   r drawn as in sanns_distances with chunk = m,
+ * q = row_query[m].  Plaintexts by dtype:
+ *   SANNS_U8, SANNS_I8  points dev [n][d]: g = -2 p (signed), P = ||p||^2;
+ *   SANNS_SHARE32       points dev [n][d] uint32, the server's shares p_s in
+ *                       [0, t) of points p = p_c + p_s mod t: g = the centred
+ *                       representative of -2 p_s mod t; norm_shares dev [n]
+ *                       uint32, its shares of ||p||^2: P = norm share.  The
+ *                       client's share is then [Dec + ||q||^2 - 2 <q, p_c> +
+ *                       ||p||^2_c]_t (its own cleartext terms).
+ *   row_query  host [M] uint32 < Q;
+ *   tail       optional resident database of dimension d (NULL for none),
+ *              scanned by every query after the gathered chunks (the stash
+ *              of the clustering-based form): rows M + q Ct + k, q < Q,
+ *              k < Ct = tail->n_chunks, are (query q, tail chunk k);
+ *   ct_in, query_ids, mask_key as sanns_distances;
+ *   ct_out     dev [M + Q Ct][2][L][N], server_share dev [M + Q Ct][N];
+ *   workspace  dev, sanns_distances_gathered_workspace(ctx, d, Q, M, tail)
+ *              bytes (the tail's residues are copied into it).
+ * The chunk word of the mask nonce is m for gathered chunk m and M + k for
+ * tail chunk k, so a (mask_key, query id) pair must not be reused across
+ * calls.  A slot index outside [-1, n) is taken as padding and a share (or
+ * norm share) >= t as 0; both set the device error word.  Errors:
+ * SANNS_E_INVALID, SANNS_E_RANGE (row_query entry >= Q, d 255^2 >= t for
+ * points), SANNS_E_WORKSPACE, SANNS_E_DEVICE. */
+sanns_status sanns_distances_gathered(sanns_ctx *ctx, const void *points, int dtype,
+                                      uint64_t n, uint32_t d,
+                                      const uint32_t *norm_shares,
+                                      const int64_t *slot_point,
+                                      const uint32_t *row_query, uint32_t M,
+                                      const sanns_db *tail, const uint64_t *ct_in,
+                                      uint32_t Q, const uint8_t *mask_key,
+                                      const uint64_t *query_ids, uint64_t *ct_out,
+                                      uint32_t *server_share, void *workspace,
+                                      size_t ws_bytes, void *stream);
+size_t sanns_distances_gathered_workspace(const sanns_ctx *ctx, uint32_t d, uint32_t Q,
+                                          uint32_t M, const sanns_db *tail);
+
+/* ------------------------------------------------------------------------
+ * Server preprocessing: k-means of the balanced clustering (Section 3.3
+ * "Balanced Clustering and Stash"; Lloyd's k-means, Section 2).  Exact
+ * integer arithmetic: points int8 [n][d] (d <= 256; uint8 data shifted by
+ * -128 first, which moves no point relative to another), centres int32
+ * [k][d] on a grid of 2^-8 (the value 256 stands for 1).  These calls need no
+ * context; they run on the current device and the caller's stream.
+ * ---------------------------------------------------------------------- */
+
+/* Workspace bytes of sanns_kmeans_assign / sanns_kmeans_update (0 for a bad
+ * shape). */
+size_t sanns_kmeans_workspace(uint32_t k, uint32_t d);
+
+/* Initial centres C_j = 256 x_{idx[j]} (idx dev [k] int64, the caller's
+ * random choice of k points).  An index outside [0, n) takes point 0 and sets
+ * *bad (dev uint32) to 1.  Errors: SANNS_E_INVALID, SANNS_E_DEVICE. */
+sanns_status sanns_kmeans_init(const int8_t *points, uint64_t n, uint32_t d,
+                               const int64_t *idx, uint32_t k, int32_t *centers,
+                               uint32_t *bad, void *stream);
+
+/* Assignment step: assign[p] = argmin_j ||256 x_p - C_j||^2 over the k
+ * centres (dev int32 [k][d]), ties to the lower index, into assign (dev int32
+ * [n]).  With prev (dev int32 [n], may be NULL) and changed (dev uint32, may
+ * be NULL), *changed is incremented by the number of points whose centre
+ * differs from prev.  Errors: SANNS_E_INVALID, SANNS_E_WORKSPACE,
+ * SANNS_E_DEVICE. */
+sanns_status sanns_kmeans_assign(const int8_t *points, uint64_t n, uint32_t d,
+                                 const int32_t *centers, uint32_t k,
+                                 const int32_t *prev, int32_t *assign,
+                                 uint32_t *changed, void *workspace,
+                                 size_t ws_bytes, void *stream);
+
+/* Update step: every centre with n_j > 0 points becomes
+ * floor(256 S_j / n_j + 1/2) (S_j the exact coordinate sums); a centre with
+ * no point keeps its value.  counts (dev int64 [k], may be NULL) receives
+ * n_j.  Assignments outside [0, k) are ignored.  Errors: as
+ * sanns_kmeans_assign. */
+sanns_status sanns_kmeans_update(const int8_t *points, uint64_t n, uint32_t d,
+                                 const int32_t *assign, uint32_t k, int32_t *centers,
+                                 int64_t *counts, void *workspace, size_t ws_bytes,
+                                 void *stream);
+
 /* Circuit-private form of sanns_distances (Section 2.3: the server's result
  * must reveal nothing beyond its plaintext, by noise flooding; Section 5
  * "Parameters", statistical circuit privacy).  Every output ciphertext f of
@@ -371,7 +461,8 @@ sanns_status sanns_distances_noalloc(sanns_ctx *ctx, const sanns_db *db,
  * word: SANNS_E_RANGE if, since the last call, an input residue was >= q_l
  * or a slot index of sanns_encode_db was outside [-1, n) (such a slot is
  * encoded as padding); SANNS_E_DEVICE if a persistent launch gave up waiting
- * for a phase (its bounded wait expired; outputs are undefined). */
+ * for a phase (its bounded wait expired; outputs are undefined); SANNS_E_RANGE
+ * also when a share given to sanns_distances_gathered was >= t. */
 sanns_status sanns_device_status(sanns_ctx *ctx, void *stream);
 
 /* Fix the multiply-accumulate schedule (used by the autotuner):

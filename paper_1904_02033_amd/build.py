@@ -13,7 +13,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsanns.so")
-SOURCES = ["kernels.hip", "mfma.hip", "sanns_api.hip", "params.cpp"]
+SOURCES = ["kernels.hip", "mfma.hip", "kmeans.hip", "sanns_api.hip", "params.cpp"]
 ARCH = os.environ.get("SANNS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

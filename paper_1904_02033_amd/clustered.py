@@ -74,18 +74,37 @@ def pack_clusters(cluster_sizes: np.ndarray, stash_size: int, N: int,
 
 
 class ClusteredServer:
-    """Resident centre and point databases of one clustered index."""
+    """Resident centre and point databases of one clustered index.
+
+    resident (gathered=False): the points are one resident NTT-form database
+    packed cluster by cluster, and phase 2 scans the chunks that hold each
+    query's clusters (shared chunks carry other clusters' points too).
+    gathered=True: the points stay on the device as they are; phase 2 packs
+    each query's selected clusters into fresh chunks, encoded on the fly, and
+    scans the stash (its own resident database) in the same call
+    (sanns_distances_gathered with the stash as its tail)."""
 
     def __init__(self, ctx: stage.Context, points: np.ndarray, cluster_sizes: np.ndarray,
                  centers: np.ndarray, stash_size: int, center_perm: np.ndarray,
-                 stash_perm: np.ndarray, key_points: bytes, key_centers: bytes):
+                 stash_perm: np.ndarray, key_points: bytes, key_centers: bytes,
+                 gathered: bool = False):
         if key_points == key_centers:
             raise ValueError("the two resident databases need distinct mask keys")
         self.ctx = ctx
         N = ctx.N
+        self.gathered = gathered
         self.n_clusters = len(cluster_sizes)
         self.layout = pack_clusters(cluster_sizes, stash_size, N, stash_perm)
-        self.db = stage.encode_db(ctx, points, self.layout.slot_point)
+        if gathered:
+            dev = torch.device("cuda", ctx.device)
+            self.pts_dev = torch.as_tensor(np.ascontiguousarray(points)).to(dev)
+            st = self.layout.slot_point[self.layout.stash_start:]
+            self.stash_slot = np.full((len(st) + N - 1) // N * N, -1, dtype=np.int64)
+            self.stash_slot[:len(st)] = st
+            self.sdb = stage.encode_db(ctx, points, self.stash_slot)
+            self.db = None
+        else:
+            self.db = stage.encode_db(ctx, points, self.layout.slot_point)
         self.center_slot = stage.linear_slot_map(self.n_clusters, N, center_perm)
         self.cdb = stage.encode_db(ctx, centers, self.center_slot)
         self.key_points, self.key_centers = key_points, key_centers
@@ -124,6 +143,38 @@ class ClusteredServer:
         D = stage.Distances(self.ctx, self.db, ct.shape[0], work=work, mode=mode)
         out, share = D.run(ct, self.key_points, qids, stream)
         return out, share, work
+
+    # ------------------------------------------------- phase 2, gathered form
+    def gather_plan(self, selected: Sequence[Sequence[int]]):
+        """Per query, the points of its selected clusters packed into fresh
+        chunks: (slot map [M N] int64 with -1 padding, the query of each chunk
+        [M] uint32)."""
+        N = self.ctx.N
+        lay = self.layout
+        slots, rows = [], []
+        for q, cl in enumerate(selected):
+            idx = np.concatenate([np.arange(lay.cluster_start[c], lay.cluster_end[c])
+                                  for c in cl]) if len(cl) else np.zeros(0, np.int64)
+            m = max(1, (len(idx) + N - 1) // N)
+            blk = np.full(m * N, -1, dtype=np.int64)
+            blk[:len(idx)] = idx
+            slots.append(blk)
+            rows += [q] * m
+        return np.concatenate(slots), np.array(rows, dtype=np.uint32)
+
+    def point_distances_gathered(self, ct: torch.Tensor, qids: torch.Tensor,
+                                 selected: Sequence[Sequence[int]], stream=None):
+        """Phase 2 in the gathered form, one call: ((ct_out, shares, slot
+        map, chunk queries) of the selected clusters' fresh chunks, (ct_out,
+        shares) of the stash for every query, rows q Cs + k)."""
+        if not self.gathered:
+            raise ValueError("the index was built without gathered=True")
+        slot, rq = self.gather_plan(selected)
+        out, share = stage.gathered_distances(self.ctx, self.pts_dev, slot, rq, ct,
+                                              self.key_points, qids, tail=self.sdb,
+                                              stream=stream)
+        M = len(rq)
+        return (out[:M], share[:M], slot, rq), (out[M:], share[M:])
 
     def requested_pairs(self, selected: Sequence[Sequence[int]]) -> int:
         """Encrypted distances that phase 2 delivers for requested points."""

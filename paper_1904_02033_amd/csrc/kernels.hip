@@ -1167,11 +1167,68 @@ k_gather(const uint8_t* __restrict__ pts, int is_signed, long n, int d,
   norms[base + g] = nrm;
 }
 
+// Gathered chunks of one call (per-query chunks of retrieved points): as
+// k_gather, into 32-bit plaintext coefficients, for kind 0 / 1 (uint8 /
+// int8 points: -2 p[i] and ||p||^2) or kind 2: the server's additive shares
+// p_s in [0, t) of secret-shared points and of their squared norms, where the
+// coefficient is the centred representative of -2 p_s mod t in
+// (-t/2, t/2] and the norm plane holds the norm share.  A share >= t sets
+// error bit 8 and is taken as 0.
+__global__ void __launch_bounds__(256)
+k_gather32(const void* __restrict__ pts, int kind, long n, int d,
+           const uint32_t* __restrict__ norm_shares, uint32_t t,
+           const int64_t* __restrict__ slot_point, long base, long total, int logN,
+           int32_t* __restrict__ gt, uint32_t* __restrict__ norms, uint32_t* err) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  const int N = 1 << logN;
+  const long k = g >> logN;
+  const int j = (int)(g & (N - 1));
+  long pid = slot_point[base + g];
+  if (pid >= n || pid < -1) {
+    if (err) atomicOr(err, 2u);
+    pid = -1;
+  }
+  int32_t* col = gt + (size_t)k * d * N + j;
+  uint32_t nrm = 0;
+  bool bad = false;
+  if (pid < 0) {
+    for (int i = 0; i < d; ++i) col[(size_t)i * N] = 0;
+  } else if (kind == 2) {
+    const uint32_t* row = reinterpret_cast<const uint32_t*>(pts) + (size_t)pid * d;
+    for (int i = 0; i < d; ++i) {
+      uint32_t x = row[i];
+      if (x >= t) {
+        bad = true;
+        x = 0;
+      }
+      const uint64_t two = (2ull * x) % t;
+      int64_t v = two ? (int64_t)t - (int64_t)two : 0;  // -2 x mod t in [0, t)
+      if (v > (int64_t)(t / 2)) v -= t;
+      col[(size_t)i * N] = (int32_t)v;
+    }
+    nrm = norm_shares[pid];
+    if (nrm >= t) {
+      bad = true;
+      nrm = 0;
+    }
+  } else {
+    const uint8_t* row = reinterpret_cast<const uint8_t*>(pts) + (size_t)pid * d;
+    for (int i = 0; i < d; ++i) {
+      const int x = kind == 1 ? (int)(int8_t)row[i] : (int)row[i];
+      col[(size_t)i * N] = -2 * x;
+      nrm += (uint32_t)(x * x);
+    }
+  }
+  if (bad && err) atomicOr(err, 8u);
+  norms[base + g] = nrm;
+}
+
 // Workgroup per (l, k, i) with k in [k0, k0 + nk): lift the signed
 // plaintext row mod q_l, forward NTT, store as 27-bit halves.
-template <int LOGN>
+template <int LOGN, typename G>
 __global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
-k_encode_ntt(const int16_t* __restrict__ gt, uint2* __restrict__ dbres, int k0, int nk, int C,
+k_encode_ntt(const G* __restrict__ gt, uint2* __restrict__ dbres, int k0, int nk, int C,
              int d, int L, PrimeSet ps, TwSet tws) {
   extern __shared__ uint64_t lds[];
   constexpr int N = NttShape<LOGN>::N;
@@ -1181,11 +1238,11 @@ k_encode_ntt(const int16_t* __restrict__ gt, uint2* __restrict__ dbres, int k0, 
   const long ki = bl % ((long)nk * d);
   const long b = ((long)l * C + k0) * d + ki;
   const Prime& P = ps.p[l];
-  const int16_t* src = gt + (size_t)ki * N;
+  const G* src = gt + (size_t)ki * N;
   uint64_t v[16];
 #pragma unroll
   for (int a = 0; a < 16; ++a) {
-    const int x = src[coef_index<LOGN>(tid, a)];
+    const int64_t x = src[coef_index<LOGN>(tid, a)];
     v[a] = x < 0 ? P.q - (uint64_t)(-x) : (uint64_t)x;
   }
   ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P);
@@ -1773,21 +1830,44 @@ hipError_t launch_gather(const void* pts, int is_signed, long n, int d,
   return hipGetLastError();
 }
 
-hipError_t launch_encode_ntt(const int16_t* gt, uint2* dbres, int k0, int nk, int C, int d,
-                             int logN, int L, const PrimeSet& ps, const TwSet& tws,
-                             hipStream_t st) {
+template <typename G>
+static hipError_t launch_encode_ntt_t(const G* gt, uint2* dbres, int k0, int nk, int C, int d,
+                                      int logN, int L, const PrimeSet& ps, const TwSet& tws,
+                                      hipStream_t st) {
   const unsigned grid = (unsigned)((long)L * nk * d);
   if (grid == 0) return hipSuccess;
   switch (logN) {
-#define SANNS_CASE(LG)                                                                \
-  case LG:                                                                            \
-    ntt_launch<LG>(k_encode_ntt<LG>, grid, st, gt, dbres, k0, nk, C, d, L, ps, tws);   \
+#define SANNS_CASE(LG)                                                                     \
+  case LG:                                                                                 \
+    ntt_launch<LG>(k_encode_ntt<LG, G>, grid, st, gt, dbres, k0, nk, C, d, L, ps, tws);     \
     break;
     SANNS_LOGN_CASES(SANNS_CASE)
 #undef SANNS_CASE
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_ntt(const int16_t* gt, uint2* dbres, int k0, int nk, int C, int d,
+                             int logN, int L, const PrimeSet& ps, const TwSet& tws,
+                             hipStream_t st) {
+  return launch_encode_ntt_t(gt, dbres, k0, nk, C, d, logN, L, ps, tws, st);
+}
+
+hipError_t launch_encode_ntt32(const int32_t* gt, uint2* dbres, int k0, int nk, int C, int d,
+                               int logN, int L, const PrimeSet& ps, const TwSet& tws,
+                               hipStream_t st) {
+  return launch_encode_ntt_t(gt, dbres, k0, nk, C, d, logN, L, ps, tws, st);
+}
+
+hipError_t launch_gather32(const void* pts, int kind, long n, int d, const uint32_t* norm_shares,
+                           uint32_t t, const int64_t* slot_point, long base, long total,
+                           int logN, int32_t* gt, uint32_t* norms, uint32_t* err,
+                           hipStream_t st) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather32, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, pts,
+                     kind, n, d, norm_shares, t, slot_point, base, total, logN, gt, norms, err);
   return hipGetLastError();
 }
 

@@ -105,11 +105,31 @@ hipError_t launch_sums_to_ct(const uint64_t* sums, uint64_t* ct_out, int Q, int 
 hipError_t launch_gather(const void* pts, int is_signed, long n, int d,
                          const int64_t* slot_point, long base, long total, int logN,
                          int16_t* gt, uint32_t* norms, uint32_t* err, hipStream_t st);
+// Gathered chunks: kind 0 / 1 uint8 / int8 points, 2 shares in [0, t) with
+// their norm shares; 32-bit plaintext coefficients.
+hipError_t launch_gather32(const void* pts, int kind, long n, int d, const uint32_t* norm_shares,
+                           uint32_t t, const int64_t* slot_point, long base, long total,
+                           int logN, int32_t* gt, uint32_t* norms, uint32_t* err,
+                           hipStream_t st);
+hipError_t launch_encode_ntt32(const int32_t* gt, uint2* dbres, int k0, int nk, int C, int d,
+                               int logN, int L, const PrimeSet& ps, const TwSet& tws,
+                               hipStream_t st);
 hipError_t launch_encode_ntt(const int16_t* gt, uint2* dbres, int k0, int nk, int C, int d,
                              int logN, int L, const PrimeSet& ps, const TwSet& tws,
                              hipStream_t st);
 hipError_t launch_sk_ntt(const int8_t* sk, uint64_t* out, int logN, int L, const PrimeSet& ps,
                          const TwSet& tws, hipStream_t st);
+// k-means of the balanced clustering (kmeans.hip): int8 points [n][d]
+// (d <= 256), centres int32 [k][d] on a 2^-8 grid; workspace km_workspace().
+size_t km_workspace(int k, int d);
+hipError_t launch_km_init(const int8_t* X, long n, int d, const int64_t* idx, int k, int32_t* C,
+                          uint32_t* bad, hipStream_t st);
+hipError_t launch_km_assign(const int8_t* X, long n, int d, const int32_t* C, int k,
+                            const int32_t* prev, int32_t* assign, uint32_t* changed, void* ws,
+                            hipStream_t st);
+hipError_t launch_km_update(const int8_t* X, long n, int d, const int32_t* assign, int k,
+                            int32_t* C, int64_t* counts_out, void* ws, hipStream_t st);
+
 // Client randomness from a seed: ternary secret [N]; uniform a [Qd][L][N]
 // and errors e [Qd][N] of Qd = Q d encrypted coordinates.
 hipError_t launch_keygen(uint64_t seed, int N, int8_t* sk, hipStream_t st);

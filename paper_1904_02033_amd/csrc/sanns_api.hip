@@ -466,6 +466,7 @@ extern "C" sanns_status sanns_device_status(sanns_ctx* ctx, void* stream) {
   HIP_TRY(hipMemset(ctx->d_err, 0, sizeof v));
   if (v & 1u) return fail(SANNS_E_RANGE, "an input residue was >= its prime");
   if (v & 2u) return fail(SANNS_E_RANGE, "a slot index was outside [-1, n)");
+  if (v & 8u) return fail(SANNS_E_RANGE, "a point or norm share was >= t");
   if (v & 4u) return fail(SANNS_E_DEVICE, "the persistent schedule timed out waiting for a phase");
   return SANNS_OK;
 }
@@ -1052,6 +1053,178 @@ extern "C" sanns_status sanns_distances(sanns_ctx* ctx, const sanns_db* db,
                                         void* workspace, size_t ws_bytes, void* stream) {
   return distances_impl(ctx, db, ct_in, Q, mask_key, query_ids, work, M, mode, ct_out,
                         server_share, workspace, ws_bytes, stream, false);
+}
+
+// ---------------------------------------------------------------------------
+// gathered chunks: per-call chunks of retrieved points (or of secret shares)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// Chunks encoded per gather/encode round (their 32-bit plaintexts stay below
+// 64 MiB).
+uint32_t gather_batch(uint32_t d, uint32_t N, uint32_t M) {
+  return std::max<uint32_t>(1, std::min<uint32_t>(M, (64u << 20) / (d * N * 4)));
+}
+
+struct GatherLayout {
+  size_t db, gt, inner, total, db_bytes;
+};
+
+// Ct: chunks of the resident tail database appended to the call's chunks.
+GatherLayout gather_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M,
+                           uint32_t Ct) {
+  const size_t N = ctx->p.N, L = ctx->p.L, C = (size_t)M + Ct;
+  GatherLayout g;
+  g.db = 0;
+  g.db_bytes = L * C * d * N * 8 + C * N * 4;  // residues, then norms
+  g.gt = align256(g.db_bytes);
+  g.inner = g.gt + align256((size_t)gather_batch(d, (uint32_t)N, M) * d * N * 4);
+  g.total = g.inner + ws_layout(ctx, d, Q, M + Q * Ct, false).total;
+  return g;
+}
+
+}  // namespace
+
+extern "C" size_t sanns_distances_gathered_workspace(const sanns_ctx* ctx, uint32_t d, uint32_t Q,
+                                                     uint32_t M, const sanns_db* tail) {
+  if (!ctx || d == 0 || M == 0) return 0;
+  return gather_layout(ctx, d, Q, M, tail ? tail->n_chunks : 0).total;
+}
+
+extern "C" sanns_status sanns_distances_gathered(
+    sanns_ctx* ctx, const void* points, int dtype, uint64_t n, uint32_t d,
+    const uint32_t* norm_shares, const int64_t* slot_point, const uint32_t* row_query,
+    uint32_t M, const sanns_db* tail, const uint64_t* ct_in, uint32_t Q,
+    const uint8_t* mask_key, const uint64_t* query_ids, uint64_t* ct_out,
+    uint32_t* server_share, void* workspace, size_t ws_bytes, void* stream) {
+  if (!ctx || !points || !slot_point || !row_query || !ct_in || !mask_key || !query_ids ||
+      !ct_out || !server_share || !workspace)
+    return fail(SANNS_E_INVALID, "null argument");
+  if (tail && (!tail->mem || tail->d != d || tail->n_chunks == 0))
+    return fail(SANNS_E_INVALID, "the tail database must have dimension d and chunks");
+  if (dtype != SANNS_U8 && dtype != SANNS_I8 && dtype != SANNS_SHARE32)
+    return fail(SANNS_E_INVALID, "bad dtype");
+  if (dtype == SANNS_SHARE32 && !norm_shares)
+    return fail(SANNS_E_INVALID, "SANNS_SHARE32 needs the norm shares");
+  if (n == 0 || d == 0 || d > SANNS_MAX_D || Q == 0 || M == 0)
+    return fail(SANNS_E_INVALID, "bad shape (n=%llu, d=%u, Q=%u, M=%u)", (unsigned long long)n,
+                d, Q, M);
+  if (dtype != SANNS_SHARE32 && (uint64_t)d * 255ull * 255ull >= ctx->p.t)
+    return fail(SANNS_E_RANGE, "d * 255^2 = %llu does not fit below t",
+                (unsigned long long)d * 65025ull);
+  for (uint32_t m = 0; m < M; ++m)
+    if (row_query[m] >= Q)
+      return fail(SANNS_E_RANGE, "row_query[%u] = %u outside [0, Q)", m, row_query[m]);
+  const uint32_t Ct = tail ? tail->n_chunks : 0, C = M + Ct;
+  const uint64_t rows = (uint64_t)M + (uint64_t)Q * Ct;
+  if (rows > 0x7FFFFFFFull) return fail(SANNS_E_INVALID, "too many output rows");
+  const GatherLayout G = gather_layout(ctx, d, Q, M, Ct);
+  if (ws_bytes < G.total)
+    return fail(SANNS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes, G.total);
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  const uint32_t N = ctx->p.N, L = ctx->p.L;
+  char* ws = (char*)workspace;
+  uint2* res = (uint2*)(ws + G.db);
+  uint32_t* norms = (uint32_t*)(ws + G.db + (size_t)L * C * d * N * 8);
+  int32_t* gt = (int32_t*)(ws + G.gt);
+  const uint32_t batch = gather_batch(d, N, M);
+  const int kind = dtype == SANNS_SHARE32 ? 2 : (dtype == SANNS_I8 ? 1 : 0);
+  for (uint32_t k0 = 0; k0 < M; k0 += batch) {
+    const uint32_t nk = std::min(batch, M - k0);
+    HIP_TRY(launch_gather32(points, kind, (long)n, (int)d, norm_shares, (uint32_t)ctx->p.t,
+                            slot_point, (long)k0 * N, (long)nk * N, ctx->logN, gt, norms,
+                            ctx->d_err, st));
+    HIP_TRY(launch_encode_ntt32(gt, res, (int)k0, (int)nk, (int)C, (int)d, ctx->logN, (int)L,
+                                ctx->ps, ctx->tws, st));
+  }
+  if (Ct) {
+    // the tail's resident NTT form and norms follow the gathered chunks
+    const size_t plane = (size_t)d * N;  // uint2 words of one chunk and limb
+    const uint2* tres = (const uint2*)tail->mem;
+    for (uint32_t l = 0; l < L; ++l)
+      HIP_TRY(hipMemcpyAsync(res + ((size_t)l * C + M) * plane, tres + (size_t)l * Ct * plane,
+                             (size_t)Ct * plane * sizeof(uint2), hipMemcpyDeviceToDevice, st));
+    const uint32_t* tnorms = (const uint32_t*)((const char*)tail->mem + (size_t)L * Ct * plane * 8);
+    HIP_TRY(hipMemcpyAsync(norms + (size_t)M * N, tnorms, (size_t)Ct * N * 4,
+                           hipMemcpyDeviceToDevice, st));
+  }
+  sanns_db tmp;
+  tmp.mem = res;
+  tmp.bytes = G.db_bytes;
+  tmp.n_chunks = C;
+  tmp.d = d;
+  std::vector<uint32_t> work(2 * (size_t)rows);
+  for (uint32_t m = 0; m < M; ++m) {
+    work[2 * m] = row_query[m];
+    work[2 * m + 1] = m;
+  }
+  for (uint32_t q = 0; q < Q; ++q)
+    for (uint32_t k = 0; k < Ct; ++k) {
+      const size_t r = (size_t)M + (size_t)q * Ct + k;
+      work[2 * r] = q;
+      work[2 * r + 1] = M + k;
+    }
+  return distances_impl(ctx, &tmp, ct_in, Q, mask_key, query_ids, work.data(), (uint32_t)rows,
+                        SANNS_MODE_FUSED, ct_out, server_share, ws + G.inner, G.total - G.inner,
+                        stream, false);
+}
+
+// ---------------------------------------------------------------------------
+// k-means of the balanced clustering
+// ---------------------------------------------------------------------------
+
+extern "C" size_t sanns_kmeans_workspace(uint32_t k, uint32_t d) {
+  if (k == 0 || d == 0 || d > 256) return 0;
+  return km_workspace((int)k, (int)d);
+}
+
+namespace {
+sanns_status km_check(const int8_t* points, uint64_t n, uint32_t d, uint32_t k, size_t ws_bytes,
+                      const void* ws) {
+  if (!points || !ws) return fail(SANNS_E_INVALID, "null argument");
+  if (n == 0 || d == 0 || d > 256 || k == 0 || n >= (1ull << 40) || k >= (1u << 30))
+    return fail(SANNS_E_INVALID, "bad shape (n=%llu, d=%u, k=%u)", (unsigned long long)n, d, k);
+  if (ws_bytes < km_workspace((int)k, (int)d))
+    return fail(SANNS_E_WORKSPACE, "workspace %zu < %zu bytes", ws_bytes,
+                km_workspace((int)k, (int)d));
+  return SANNS_OK;
+}
+}  // namespace
+
+extern "C" sanns_status sanns_kmeans_init(const int8_t* points, uint64_t n, uint32_t d,
+                                          const int64_t* idx, uint32_t k, int32_t* centers,
+                                          uint32_t* bad, void* stream) {
+  if (!points || !idx || !centers || !bad) return fail(SANNS_E_INVALID, "null argument");
+  if (n == 0 || d == 0 || d > 256 || k == 0) return fail(SANNS_E_INVALID, "bad shape");
+  HIP_TRY(launch_km_init(points, (long)n, (int)d, idx, (int)k, centers, bad, (hipStream_t)stream));
+  return SANNS_OK;
+}
+
+extern "C" sanns_status sanns_kmeans_assign(const int8_t* points, uint64_t n, uint32_t d,
+                                            const int32_t* centers, uint32_t k,
+                                            const int32_t* prev, int32_t* assign,
+                                            uint32_t* changed, void* workspace,
+                                            size_t ws_bytes, void* stream) {
+  sanns_status s = km_check(points, n, d, k, ws_bytes, workspace);
+  if (s != SANNS_OK) return s;
+  if (!centers || !assign) return fail(SANNS_E_INVALID, "null argument");
+  HIP_TRY(launch_km_assign(points, (long)n, (int)d, centers, (int)k, prev, assign, changed,
+                           workspace, (hipStream_t)stream));
+  return SANNS_OK;
+}
+
+extern "C" sanns_status sanns_kmeans_update(const int8_t* points, uint64_t n, uint32_t d,
+                                            const int32_t* assign, uint32_t k, int32_t* centers,
+                                            int64_t* counts, void* workspace, size_t ws_bytes,
+                                            void* stream) {
+  sanns_status s = km_check(points, n, d, k, ws_bytes, workspace);
+  if (s != SANNS_OK) return s;
+  if (!centers || !assign) return fail(SANNS_E_INVALID, "null argument");
+  HIP_TRY(launch_km_update(points, (long)n, (int)d, assign, (int)k, centers, counts, workspace,
+                           (hipStream_t)stream));
+  return SANNS_OK;
 }
 
 extern "C" uint32_t sanns_flood_bits(const sanns_ctx* ctx) {

@@ -30,7 +30,7 @@ SANNS_MAX_D = 4096
 SANNS_FLAG_INSECURE_TEST = 1
 SANNS_FLAG_DIGIT_DB = 2
 SANNS_SCHEDULE_MFMA = 81
-SANNS_U8, SANNS_I8 = 0, 1
+SANNS_U8, SANNS_I8, SANNS_SHARE32 = 0, 1, 2
 SANNS_MODE_PLAIN, SANNS_MODE_FUSED, SANNS_MODE_BATCHED, SANNS_MODE_PERSISTENT = 0, 1, 2, 3
 
 # Every exported symbol of include/sanns.h.
@@ -41,7 +41,9 @@ EXPORTS = [
     "sanns_distances", "sanns_device_status", "sanns_set_schedule",
     "sanns_profile_enable", "sanns_profile_read", "sanns_distances_noalloc",
     "sanns_keygen", "sanns_encrypt_query_seeded", "sanns_public_key", "sanns_distances_cp",
-    "sanns_distances_cp_workspace", "sanns_flood_bits",
+    "sanns_distances_cp_workspace", "sanns_flood_bits", "sanns_distances_gathered",
+    "sanns_distances_gathered_workspace", "sanns_kmeans_workspace", "sanns_kmeans_init",
+    "sanns_kmeans_assign", "sanns_kmeans_update",
 ]
 SANNS_NOALLOC_SCRATCH_BYTES = 64 << 20
 SANNS_N_PHASES = 7
@@ -108,6 +110,21 @@ def load() -> ctypes.CDLL:
     L.sanns_distances_cp.restype = st
     L.sanns_distances_cp_workspace.argtypes = [vp, ctypes.POINTER(sanns_db), u32, u32, i32]
     L.sanns_distances_cp_workspace.restype = ctypes.c_size_t
+    L.sanns_distances_gathered.argtypes = [vp, vp, i32, u64, u32, vp, vp, vp, u32,
+                                           ctypes.POINTER(sanns_db), vp, u32, ctypes.c_char_p,
+                                           vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.sanns_distances_gathered.restype = st
+    L.sanns_distances_gathered_workspace.argtypes = [vp, u32, u32, u32,
+                                                     ctypes.POINTER(sanns_db)]
+    L.sanns_distances_gathered_workspace.restype = ctypes.c_size_t
+    L.sanns_kmeans_workspace.argtypes = [u32, u32]
+    L.sanns_kmeans_workspace.restype = ctypes.c_size_t
+    L.sanns_kmeans_init.argtypes = [vp, u64, u32, vp, u32, vp, vp, vp]
+    L.sanns_kmeans_init.restype = st
+    L.sanns_kmeans_assign.argtypes = [vp, u64, u32, vp, u32, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.sanns_kmeans_assign.restype = st
+    L.sanns_kmeans_update.argtypes = [vp, u64, u32, vp, u32, vp, vp, vp, ctypes.c_size_t, vp]
+    L.sanns_kmeans_update.restype = st
     L.sanns_flood_bits.argtypes = [vp]
     L.sanns_flood_bits.restype = u32
     L.sanns_decrypt_shares.argtypes = [vp, vp, vp, u32, vp, vp, vp]
@@ -206,6 +223,49 @@ def sanns_distances_cp(ctx: int, db: sanns_db, ct_in: int, Q: int, mask_key: byt
 
 def sanns_distances_cp_workspace(ctx: int, db: sanns_db, Q: int, M: int, mode: int) -> int:
     return load().sanns_distances_cp_workspace(ctx, ctypes.byref(db), Q, M, mode)
+
+
+def sanns_distances_gathered(ctx: int, points: int, dtype: int, n: int, d: int,
+                             norm_shares: int, slot_point: int, row_query, M: int, tail,
+                             ct_in: int, Q: int, mask_key: bytes, query_ids: int, ct_out: int,
+                             server_share: int, workspace: int, ws_bytes: int,
+                             stream: int = 0) -> None:
+    """``row_query`` is a C-contiguous host numpy uint32 array [M]; ``tail``
+    a sanns_db or None."""
+    if len(mask_key) != 32:
+        raise ValueError("mask_key must be 32 bytes")
+    _check(load().sanns_distances_gathered(
+        ctx, points, dtype, n, d, norm_shares, slot_point,
+        row_query.ctypes.data_as(ctypes.c_void_p), M,
+        None if tail is None else ctypes.byref(tail), ct_in, Q, mask_key, query_ids, ct_out,
+        server_share, workspace, ws_bytes, stream))
+
+
+def sanns_distances_gathered_workspace(ctx: int, d: int, Q: int, M: int, tail=None) -> int:
+    return load().sanns_distances_gathered_workspace(
+        ctx, d, Q, M, None if tail is None else ctypes.byref(tail))
+
+
+def sanns_kmeans_workspace(k: int, d: int) -> int:
+    return load().sanns_kmeans_workspace(k, d)
+
+
+def sanns_kmeans_init(points: int, n: int, d: int, idx: int, k: int, centers: int, bad: int,
+                      stream: int = 0) -> None:
+    _check(load().sanns_kmeans_init(points, n, d, idx, k, centers, bad, stream))
+
+
+def sanns_kmeans_assign(points: int, n: int, d: int, centers: int, k: int, prev: int,
+                        assign: int, changed: int, workspace: int, ws_bytes: int,
+                        stream: int = 0) -> None:
+    _check(load().sanns_kmeans_assign(points, n, d, centers, k, prev, assign, changed,
+                                      workspace, ws_bytes, stream))
+
+
+def sanns_kmeans_update(points: int, n: int, d: int, assign: int, k: int, centers: int,
+                        counts: int, workspace: int, ws_bytes: int, stream: int = 0) -> None:
+    _check(load().sanns_kmeans_update(points, n, d, assign, k, centers, counts, workspace,
+                                      ws_bytes, stream))
 
 
 def sanns_flood_bits(ctx: int) -> int:

@@ -209,6 +209,48 @@ class Distances:
         return self.ct_out, self.share
 
 
+def gathered_distances(ctx: Context, points: torch.Tensor, slot_point, row_query: np.ndarray,
+                       ct_in: torch.Tensor, mask_key: bytes, query_ids: torch.Tensor,
+                       norm_shares: Optional[torch.Tensor] = None,
+                       tail: Optional[Database] = None,
+                       workspace: Optional[torch.Tensor] = None, stream=None):
+    """sanns_distances_gathered: chunk m holds points slot_point[m N:(m+1) N]
+    (-1 padding) and belongs to query row_query[m]; with a tail database,
+    every query also scans its chunks (rows M + q Ct + k).  points: device
+    [n][d] uint8 / int8 points, or int32 / uint32 shares in [0, t) (then
+    norm_shares [n] is required).  Returns (ct_out [rows][2][L][N], shares
+    [rows][N])."""
+    if points.dtype == torch.uint8:
+        dtype = nat.SANNS_U8
+    elif points.dtype == torch.int8:
+        dtype = nat.SANNS_I8
+    elif points.dtype in (torch.int32, torch.uint32):
+        dtype = nat.SANNS_SHARE32
+    else:
+        raise ValueError("points must be uint8, int8 or 32-bit shares")
+    n, d = points.shape
+    rq = np.ascontiguousarray(row_query, dtype=np.uint32)
+    M = len(rq)
+    dev = points.device
+    sp = slot_point if isinstance(slot_point, torch.Tensor) else torch.as_tensor(
+        np.ascontiguousarray(slot_point, dtype=np.int64)).to(dev)
+    if sp.numel() != M * ctx.N:
+        raise ValueError("slot map must hold M N entries")
+    Q = ct_in.shape[0]
+    tdesc = None if tail is None else tail.desc
+    rows = M + (0 if tail is None else Q * tail.n_chunks)
+    ws_bytes = nat.sanns_distances_gathered_workspace(ctx.handle, d, Q, M, tdesc)
+    ws = workspace[:ws_bytes] if workspace is not None and workspace.numel() >= ws_bytes \
+        else torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    ct_out = torch.empty((rows, 2, ctx.L, ctx.N), dtype=torch.uint64, device=dev)
+    share = torch.empty((rows, ctx.N), dtype=torch.uint32, device=dev)
+    nat.sanns_distances_gathered(ctx.handle, _ptr(points), dtype, n, d, _ptr(norm_shares),
+                                 _ptr(sp.contiguous()), rq, M, tdesc, _ptr(ct_in), Q,
+                                 mask_key, _ptr(query_ids), _ptr(ct_out), _ptr(share), _ptr(ws),
+                                 ws_bytes, _stream(stream))
+    return ct_out, share
+
+
 def distances(ctx: Context, db: Database, ct_in: torch.Tensor, mask_key: bytes,
               query_ids: torch.Tensor, work: Optional[np.ndarray] = None,
               mode: int = nat.SANNS_MODE_FUSED, stream=None):

@@ -302,3 +302,48 @@ def test_serving_full_size_trace(cworld):
         r.outputs.clear()
         torch.cuda.empty_cache()
     ctxA.close()
+
+
+def test_clustered_full_size_gathered_phase2(cworld):
+    """Phase 2 on per-query gathered chunks plus the resident stash (the
+    form that scans only the selected clusters' points): every slot of all
+    32 queries decrypts to its distance, and sampled gathered rows equal the
+    oracle's on uniform residue inputs."""
+    W = cworld
+    nat, stage, clustered, ctx, dev = W["nat"], W["stage"], W["clustered"], W["ctx"], W["dev"]
+    cdb, Q, queries = W["cdb"], W["Q"], W["queries"]
+    gsrv = clustered.ClusteredServer(
+        ctx, cdb.points, cdb.cluster_sizes, cdb.centers, cdb.stash_size,
+        synthdata.gen_perm(len(cdb.cluster_sizes), synthdata.SEED_PERM + 4),
+        synthdata.gen_perm(cdb.stash_size, synthdata.SEED_PERM + 40),
+        synthdata.gen_mask_key(synthdata.SEED_MASK + 41), W["srv"].key_centers, gathered=True)
+    (co, cs, slot, rq), (so, ss) = gsrv.point_distances_gathered(W["ct"], W["qids"],
+                                                                 W["selected"])
+    torch.cuda.synchronize()
+    ctx.device_status()
+    n1 = _closed_form(stage, ctx, W["sk"], co, cs, queries[rq], np.arange(len(rq)), slot,
+                      cdb.points, dev)
+    assert n1 == W["srv"].requested_pairs(W["selected"]) - Q * cdb.stash_size
+    Cs = gsrv.sdb.n_chunks
+    n2 = _closed_form(stage, ctx, W["sk"], so, ss, np.repeat(queries, Cs, 0),
+                      np.tile(np.arange(Cs), Q), gsrv.stash_slot, cdb.points, dev)
+    assert n2 == Q * cdb.stash_size
+    del co, cs, so, ss
+    # oracle rows on uniform residue inputs
+    N, L, d = ctx.N, ctx.L, cdb.points.shape[1]
+    P = oracle.Params(N, oracle.rns_primes(N, L), oracle.plain_modulus(N, W["w"].t_bits))
+    ct_host = synthdata.gen_uniform_a(P.qs, N, Q * d * 2, 93).reshape(Q, d, 2, L, N)
+    qids = torch.as_tensor(np.arange(7000, 7000 + Q, dtype=np.uint64)).to(dev)
+    (co, cs, slot, rq), _ = gsrv.point_distances_gathered(torch.as_tensor(ct_host).to(dev), qids,
+                                                          W["selected"])
+    torch.cuda.synchronize()
+    g = np.random.default_rng(94)
+    js = sorted(set([0, N - 1] + [int(x) for x in g.integers(0, N, 16)]))
+    last = int(np.nonzero(rq == Q - 1)[0][-1])
+    for m in sorted(set([0, last, int(g.integers(0, len(rq)))])):
+        qi = int(rq[m])
+        want_r = oracle.masks(gsrv.key_points, 7000 + qi, m, P.t, N)
+        assert (cs[m].cpu().numpy() == want_r).all(), m
+        gk, nrm = oracle.chunk_plaintexts(cdb.points, slot, N, m)
+        sc, _ = oracle.server_coeffs(P, ct_host[qi], gk, nrm, gsrv.key_points, 7000 + qi, m, js)
+        assert (co[m].cpu().numpy()[:, :, js] == sc).all(), m
