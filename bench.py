@@ -652,7 +652,7 @@ def run_clustered(args):
     m0 = int(np.nonzero(grq == 0)[0][0])
     cl = stage.decrypt_shares(ctx, sk, co[m0:m0 + 1].contiguous(),
                               torch.as_tensor(qn2[:1]).to(dev)).cpu().numpy()[0]
-    ids = gslot[m0 * ctx.N:(m0 + 1) * ctx.N]
+    ids = gslot[m0 * ctx.N:(m0 + 1) * ctx.N].cpu().numpy()
     real = ids >= 0
     want = ((cdb.points[ids[real]].astype(np.int64) - queries[0]) ** 2).sum(axis=1)
     assert (((cl.astype(np.int64) + cs[m0].cpu().numpy()) % ctx.t)[real] == want).all()

@@ -349,6 +349,14 @@ sanns_status sanns_distances_gathered(sanns_ctx *ctx, const void *points, int dt
 size_t sanns_distances_gathered_workspace(const sanns_ctx *ctx, uint32_t d, uint32_t Q,
                                           uint32_t M, const sanns_db *tail);
 
+/* Slot map of gathered chunks built on the device from point ranges (the
+ * points of retrieved clusters are contiguous runs of the point array):
+ * slot_point[0 .. total) = -1, then slot_point[off[r] + i] = start[r] + i
+ * for i < len[r], r < R (start, len, off dev [R] int64; writes outside
+ * [0, total) are dropped).  Errors: SANNS_E_INVALID, SANNS_E_DEVICE. */
+sanns_status sanns_slot_ranges(const int64_t *start, const int64_t *len, const int64_t *off,
+                               uint32_t R, int64_t *slot_point, uint64_t total, void *stream);
+
 /* ------------------------------------------------------------------------
  * Server preprocessing: k-means of the balanced clustering (Section 3.3
  * "Balanced Clustering and Stash"; Lloyd's k-means, Section 2).  Exact
@@ -425,7 +433,8 @@ sanns_status sanns_distances_cp(sanns_ctx *ctx, const sanns_db *db,
                                 size_t ws_bytes, void *stream);
 
 /* Workspace bytes of sanns_distances_cp (that of sanns_distances plus the
- * public keys' NTT form, Q 2 L N 8 bytes). */
+ * public keys' NTT form, Q 2 L N 8 bytes, and the noise of the outputs,
+ * M (8 L + 2) N bytes). */
 size_t sanns_distances_cp_workspace(const sanns_ctx *ctx, const sanns_db *db,
                                     uint32_t Q, uint32_t M, int mode);
 

@@ -162,14 +162,42 @@ class ClusteredServer:
             rows += [q] * m
         return np.concatenate(slots), np.array(rows, dtype=np.uint32)
 
+    def gather_plan_device(self, selected: Sequence[Sequence[int]], stream=None):
+        """gather_plan built on the device from the clusters' point ranges
+        (only the R = sum of |selected| ranges cross from the host): (slot map,
+        device int64 [M N]; chunk queries [M] uint32)."""
+        N = self.ctx.N
+        lay = self.layout
+        starts, lens, offs, rows = [], [], [], []
+        base = 0
+        for q, cl in enumerate(selected):
+            cl = np.asarray(cl, dtype=np.int64)
+            st = lay.cluster_start[cl].astype(np.int64)
+            ln = (lay.cluster_end[cl] - lay.cluster_start[cl]).astype(np.int64)
+            starts.append(st)
+            lens.append(ln)
+            offs.append(base + np.concatenate([[0], np.cumsum(ln)[:-1]]).astype(np.int64))
+            m = max(1, int((ln.sum() + N - 1) // N))
+            rows += [q] * m
+            base += m * N
+        dev = torch.device("cuda", self.ctx.device)
+        host = np.stack([np.concatenate(starts), np.concatenate(lens), np.concatenate(offs)])
+        rng = torch.as_tensor(host).to(dev)
+        slot = torch.empty(base, dtype=torch.int64, device=dev)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        nat.sanns_slot_ranges(rng[0].data_ptr(), rng[1].data_ptr(), rng[2].data_ptr(),
+                              rng.shape[1], slot.data_ptr(), base, s.cuda_stream)
+        self._ranges = rng  # held until the next plan: the fill may still be queued
+        return slot, np.array(rows, dtype=np.uint32)
+
     def point_distances_gathered(self, ct: torch.Tensor, qids: torch.Tensor,
                                  selected: Sequence[Sequence[int]], stream=None):
         """Phase 2 in the gathered form, one call: ((ct_out, shares, slot
-        map, chunk queries) of the selected clusters' fresh chunks, (ct_out,
-        shares) of the stash for every query, rows q Cs + k)."""
+        map (device), chunk queries) of the selected clusters' fresh chunks,
+        (ct_out, shares) of the stash for every query, rows q Cs + k)."""
         if not self.gathered:
             raise ValueError("the index was built without gathered=True")
-        slot, rq = self.gather_plan(selected)
+        slot, rq = self.gather_plan_device(selected, stream)
         out, share = stage.gathered_distances(self.ctx, self.pts_dev, slot, rq, ct,
                                               self.key_points, qids, tail=self.sdb,
                                               stream=stream)

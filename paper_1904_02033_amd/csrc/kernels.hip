@@ -339,73 +339,79 @@ k_rerand(MaskKey K, const uint64_t* __restrict__ qids, const uint32_t* __restric
   }
 }
 
-// k_intt_mask with the re-randomisation's coefficient-form terms: e1, the
-// flood and Delta [norm - r]_t on c0, e2 on c1.  The errors are generated into
-// LDS for the whole polynomial; the flood (one ChaCha20 block per two
-// coefficients) a quarter of the coefficients at a time.
-// Four waves per SIMD: the flood's ChaCha20 state beside the 16 residues
-// needs more registers than k_intt_mask's bound leaves (it spilled at six).
-template <int LOGN>
-__global__ void __launch_bounds__(NttShape<LOGN>::T, 4)
-k_intt_mask_cp(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
-               const uint32_t* __restrict__ norms, const uint32_t* __restrict__ work, int C,
-               int L, uint32_t t, MaskKey K, const uint64_t* __restrict__ qids, CpConst cp,
-               DigitSet ds, PrimeSet ps, TwSet tws) {
-  extern __shared__ uint64_t lds[];
-  constexpr int N = NttShape<LOGN>::N, T = NttShape<LOGN>::T;
-  const int tid = threadIdx.x, p = blockIdx.x;
-  const int l = p % L, c = (p / L) & 1, m = p / (2 * L);
+// Thread per (output m, block b): the flood of coefficients 2b and 2b + 1
+// (one ChaCha20 block) reduced for every limb, flood[m][l][j]; threads with
+// b < N/8 also draw e1 and e2 of coefficients 8b .. 8b + 7, errs[m][c][j].
+// Generated once here instead of once per limb inside the inverse transform.
+__global__ void __launch_bounds__(256)
+k_cp_noise(MaskKey K, const uint64_t* __restrict__ qids, const uint32_t* __restrict__ work,
+           int C, long M, int N, int L, CpConst cp, DigitSet ds, PrimeSet ps,
+           uint64_t* __restrict__ flood, int8_t* __restrict__ errs) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int nb = N / 2;
+  if (g >= M * nb) return;
+  const int m = (int)(g / nb), b = (int)(g % nb);
   int qi, k;
   work_pair(work, m, C, qi, k);
   const uint64_t id = qids[qi];
   const uint32_t n0 = (uint32_t)id, n1 = (uint32_t)(id >> 32), n2 = (uint32_t)k;
+  uint32_t o[16];
+  chacha_block(K, kCpStreamFlood + (uint32_t)b, n0, n1, n2, o);
+  for (int l = 0; l < L; ++l) {
+    const uint64_t q = ps.p[l].q;
+    ulonglong2 v;
+    v.x = flood_residue(o, cp.b, cp.twob[l], ds.c[l], q);
+    v.y = flood_residue(o + 8, cp.b, cp.twob[l], ds.c[l], q);
+    reinterpret_cast<ulonglong2*>(flood + ((size_t)m * L + l) * N)[b] = v;
+  }
+  if (b < N / 8) {
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      chacha_block(K, (c == 0 ? kCpStreamE1 : kCpStreamE2) + (uint32_t)b, n0, n1, n2, o);
+      uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        w0 |= (uint32_t)(uint8_t)(int8_t)cbd21(word64_of(o, n)) << (8 * n);
+        w1 |= (uint32_t)(uint8_t)(int8_t)cbd21(word64_of(o, n + 4)) << (8 * n);
+      }
+      reinterpret_cast<uint2*>(errs + ((size_t)m * 2 + c) * N)[b] = make_uint2(w0, w1);
+    }
+  }
+}
+
+// k_intt_mask with the re-randomisation's coefficient-form terms (drawn by
+// k_cp_noise): e1, the flood and Delta [norm - r]_t on c0, e2 on c1.
+template <int LOGN>
+__global__ void __launch_bounds__(NttShape<LOGN>::T, intt_mask_waves(LOGN))
+k_intt_mask_cp(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
+               const uint32_t* __restrict__ norms, const uint32_t* __restrict__ work, int C,
+               int L, uint32_t t, const uint64_t* __restrict__ flood,
+               const int8_t* __restrict__ errs, PrimeSet ps, TwSet tws) {
+  extern __shared__ uint64_t lds[];
+  constexpr int N = NttShape<LOGN>::N;
+  const int tid = threadIdx.x, p = blockIdx.x;
+  const int l = p % L, c = (p / L) & 1, m = p / (2 * L);
   const Prime& P = ps.p[l];
   uint64_t* buf = ct + (size_t)p * N;
   uint64_t v[16];
 #pragma unroll
   for (int a = 0; a < 16; ++a) v[a] = buf[ntt_slot<LOGN>(tid, a)];
   ntt_inv<LOGN>(v, lds, tid, tws.tw[l] + N, P);
-  __syncthreads();  // the transform's LDS is free
-  int8_t* eb = reinterpret_cast<int8_t*>(lds);
-  for (int b = tid; b < N / 8; b += T) {
-    uint32_t o[16];
-    chacha_block(K, (c == 0 ? kCpStreamE1 : kCpStreamE2) + (uint32_t)b, n0, n1, n2, o);
+  const int8_t* e = errs + ((size_t)m * 2 + c) * N;
 #pragma unroll
-    for (int n = 0; n < 8; ++n) eb[8 * b + n] = (int8_t)cbd21(word64_of(o, n));
-  }
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 16; ++a)
-    v[a] = addmod(v[a], lift_small(eb[coef_index<LOGN>(tid, a)], P.q), P.q);
+  for (int a = 0; a < 16; ++a) v[a] = addmod(v[a], lift_small(e[coef_index<LOGN>(tid, a)], P.q), P.q);
   if (c == 0) {
+    int qi, k;
+    work_pair(work, m, C, qi, k);
     const uint32_t* nrm = norms + (size_t)k * N;
     const uint32_t* r = share + (size_t)m * N;
+    const uint64_t* fl = flood + ((size_t)m * L + l) * N;
 #pragma unroll
     for (int a = 0; a < 16; ++a) {
       const int j = coef_index<LOGN>(tid, a);
       const uint32_t pn = nrm[j], rj = r[j];
       const uint64_t mv = pn >= rj ? pn - rj : pn + t - rj;
-      v[a] = addmod(v[a], shoup(mv, P.delta, P.deltap, P.q), P.q);
-    }
-    uint64_t* fb = lds + N / 8;  // after the error bytes
-    const DigitConst& D = ds.c[l];
-    const uint64_t twob = cp.twob[l];
-    constexpr int Nq = N / 4;
-#pragma unroll 1
-    for (int rd = 0; rd < 4; ++rd) {
-      for (int h = tid; h < Nq / 2; h += T) {
-        uint32_t o[16];
-        chacha_block(K, kCpStreamFlood + (uint32_t)(rd * (Nq / 2) + h), n0, n1, n2, o);
-        fb[2 * h] = flood_residue(o, cp.b, twob, D, P.q);
-        fb[2 * h + 1] = flood_residue(o + 8, cp.b, twob, D, P.q);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int a = 0; a < 16; ++a) {
-        const int j = coef_index<LOGN>(tid, a) - rd * Nq;
-        if (j >= 0 && j < Nq) v[a] = addmod(v[a], fb[j], P.q);
-      }
-      __syncthreads();
+      v[a] = addmod(addmod(v[a], shoup(mv, P.delta, P.deltap, P.q), P.q), fl[j], P.q);
     }
   }
   __syncthreads();  // every thread has read its inputs before any overwrite
@@ -1861,6 +1867,33 @@ hipError_t launch_encode_ntt32(const int32_t* gt, uint2* dbres, int k0, int nk, 
   return launch_encode_ntt_t(gt, dbres, k0, nk, C, d, logN, L, ps, tws, st);
 }
 
+// Block per range r: slot[off[r] + i] = start[r] + i for i < len[r] (writes
+// past `total` are dropped); launched after slot has been filled with -1.
+__global__ void __launch_bounds__(256)
+k_slot_ranges(const int64_t* __restrict__ start, const int64_t* __restrict__ len,
+              const int64_t* __restrict__ off, int64_t* __restrict__ slot, long total) {
+  const int r = blockIdx.x;
+  const long s0 = start[r], n = len[r], o = off[r];
+  for (long i = threadIdx.x; i < n; i += blockDim.x)
+    if (o + i >= 0 && o + i < total) slot[o + i] = s0 + i;
+}
+
+__global__ void __launch_bounds__(256) k_fill_i64(int64_t* __restrict__ p, long n, int64_t v) {
+  const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) p[g] = v;
+}
+
+hipError_t launch_slot_ranges(const int64_t* start, const int64_t* len, const int64_t* off,
+                              int R, int64_t* slot, long total, hipStream_t st) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, slot,
+                     total, (int64_t)-1);
+  if (R > 0)
+    hipLaunchKernelGGL(k_slot_ranges, dim3((unsigned)R), dim3(256), 0, st, start, len, off, slot,
+                       total);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather32(const void* pts, int kind, long n, int d, const uint32_t* norm_shares,
                            uint32_t t, const int64_t* slot_point, long base, long total,
                            int logN, int32_t* gt, uint32_t* norms, uint32_t* err,
@@ -1908,13 +1941,18 @@ hipError_t launch_intt_mask_cp(uint64_t* ct, const uint32_t* share, const uint32
                                const uint32_t* work, int C, int M, int logN, int L, uint32_t t,
                                const MaskKey& K, const uint64_t* qids, const CpConst& cp,
                                const DigitSet& ds, const PrimeSet& ps, const TwSet& tws,
-                               hipStream_t st) {
+                               uint64_t* flood, hipStream_t st) {
   if (M <= 0) return hipSuccess;
+  const int N = 1 << logN;
+  const long nf = (long)M * (N / 2);
+  int8_t* errs = reinterpret_cast<int8_t*>(flood + (size_t)M * L * N);
+  hipLaunchKernelGGL(k_cp_noise, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, K, qids,
+                     work, C, (long)M, N, L, cp, ds, ps, flood, errs);
   switch (logN) {
 #define SANNS_CASE(LG)                                                                       \
   case LG:                                                                                   \
     ntt_launch<LG>(k_intt_mask_cp<LG>, (unsigned)(M * 2 * L), st, ct, share, norms, work, C, L, \
-                   t, K, qids, cp, ds, ps, tws);                                             \
+                   t, (const uint64_t*)flood, (const int8_t*)errs, ps, tws);                 \
     break;
     SANNS_LOGN_CASES(SANNS_CASE)
 #undef SANNS_CASE

@@ -105,6 +105,10 @@ hipError_t launch_sums_to_ct(const uint64_t* sums, uint64_t* ct_out, int Q, int 
 hipError_t launch_gather(const void* pts, int is_signed, long n, int d,
                          const int64_t* slot_point, long base, long total, int logN,
                          int16_t* gt, uint32_t* norms, uint32_t* err, hipStream_t st);
+// Slot map of gathered chunks from point ranges: -1 everywhere, then
+// slot[off[r] + i] = start[r] + i, i < len[r].
+hipError_t launch_slot_ranges(const int64_t* start, const int64_t* len, const int64_t* off,
+                              int R, int64_t* slot, long total, hipStream_t st);
 // Gathered chunks: kind 0 / 1 uint8 / int8 points, 2 shares in [0, t) with
 // their norm shares; 32-bit plaintext coefficients.
 hipError_t launch_gather32(const void* pts, int kind, long n, int d, const uint32_t* norm_shares,
@@ -142,11 +146,13 @@ hipError_t launch_sample_enc(uint64_t seed, uint32_t purpose_a, uint32_t purpose
 hipError_t launch_rerand(const MaskKey& K, const uint64_t* qids, const uint32_t* work, int C,
                          int M, int L, int logN, const uint64_t* pk_ntt, uint64_t* ct,
                          const PrimeSet& ps, const TwSet& tws, hipStream_t st);
+// flood: workspace [M][L][N] uint64 for the flood residues, followed by
+// [M][2][N] int8 for e1 and e2 (k_cp_noise).
 hipError_t launch_intt_mask_cp(uint64_t* ct, const uint32_t* share, const uint32_t* norms,
                                const uint32_t* work, int C, int M, int logN, int L, uint32_t t,
                                const MaskKey& K, const uint64_t* qids, const CpConst& cp,
                                const DigitSet& ds, const PrimeSet& ps, const TwSet& tws,
-                               hipStream_t st);
+                               uint64_t* flood, hipStream_t st);
 hipError_t launch_encrypt(const uint64_t* a, const int16_t* e, const int32_t* msgs,
                           const uint64_t* sk_ntt, uint64_t* ct, int Qd, int L, int logN,
                           uint32_t t, const PrimeSet& ps, const TwSet& tws, hipStream_t st);

@@ -309,7 +309,7 @@ sanns_status stage_upload(sanns_ctx* ctx, void* dst, const void* src, size_t byt
 }
 
 struct WsLayout {
-  size_t qntt, tiles, work, tmp, ctrl, qdig, sums, pkntt, total;
+  size_t qntt, tiles, work, tmp, ctrl, qdig, sums, pkntt, flood, total;
 };
 
 // mfma: the call runs the matrix-core schedule (query digits and sums regions);
@@ -338,6 +338,8 @@ WsLayout ws_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_t M, boo
   }
   w.pkntt = off;
   if (cp) off += align256((size_t)Q * 2 * L * N * 8);
+  w.flood = off;  // flood residues [M][L][N] uint64, then e1, e2 [M][2][N] int8
+  if (cp) off += align256((size_t)M * L * N * 8 + (size_t)M * 2 * N);
   w.total = off;
   return w;
 }
@@ -704,6 +706,7 @@ namespace {
 struct CpArgs {
   const uint64_t* pk = nullptr;
   uint64_t* pk_ntt = nullptr;
+  uint64_t* flood = nullptr;
   CpConst c{};
   bool on = false;
 };
@@ -770,7 +773,7 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
   if (cp.on)
     HIP_TRY(launch_intt_mask_cp(ct_out, share, norms, dwork, (int)C, (int)M, ctx->logN, (int)L,
                                 (uint32_t)ctx->p.t, K, qids, cp.c, ctx->ds, ctx->ps, ctx->tws,
-                                st));
+                                cp.flood, st));
   else
     HIP_TRY(launch_intt_mask(ct_out, share, norms, dwork, (int)C, (int)M, ctx->logN, (int)L,
                              (uint32_t)ctx->p.t, ctx->ps, ctx->tws, st));
@@ -884,6 +887,7 @@ sanns_status distances_impl(sanns_ctx* ctx, const sanns_db* db, const uint64_t* 
     cp.on = true;
     cp.pk = pk;
     cp.pk_ntt = (uint64_t*)(ws + W.pkntt);
+    cp.flood = (uint64_t*)(ws + W.flood);
     cp.c.b = (int)flood_bits;
     for (uint32_t l = 0; l < ctx->p.L; ++l) cp.c.twob[l] = host::pow2_mod((int)flood_bits, ctx->p.q[l]);
   }
@@ -1085,6 +1089,15 @@ GatherLayout gather_layout(const sanns_ctx* ctx, uint32_t d, uint32_t Q, uint32_
 }
 
 }  // namespace
+
+extern "C" sanns_status sanns_slot_ranges(const int64_t* start, const int64_t* len,
+                                          const int64_t* off, uint32_t R, int64_t* slot_point,
+                                          uint64_t total, void* stream) {
+  if (!slot_point || (R && (!start || !len || !off))) return fail(SANNS_E_INVALID, "null argument");
+  if (total > (1ull << 40)) return fail(SANNS_E_INVALID, "total too large");
+  HIP_TRY(launch_slot_ranges(start, len, off, (int)R, slot_point, (long)total, (hipStream_t)stream));
+  return SANNS_OK;
+}
 
 extern "C" size_t sanns_distances_gathered_workspace(const sanns_ctx* ctx, uint32_t d, uint32_t Q,
                                                      uint32_t M, const sanns_db* tail) {

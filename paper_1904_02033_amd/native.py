@@ -43,7 +43,7 @@ EXPORTS = [
     "sanns_keygen", "sanns_encrypt_query_seeded", "sanns_public_key", "sanns_distances_cp",
     "sanns_distances_cp_workspace", "sanns_flood_bits", "sanns_distances_gathered",
     "sanns_distances_gathered_workspace", "sanns_kmeans_workspace", "sanns_kmeans_init",
-    "sanns_kmeans_assign", "sanns_kmeans_update",
+    "sanns_kmeans_assign", "sanns_kmeans_update", "sanns_slot_ranges",
 ]
 SANNS_NOALLOC_SCRATCH_BYTES = 64 << 20
 SANNS_N_PHASES = 7
@@ -117,6 +117,8 @@ def load() -> ctypes.CDLL:
     L.sanns_distances_gathered_workspace.argtypes = [vp, u32, u32, u32,
                                                      ctypes.POINTER(sanns_db)]
     L.sanns_distances_gathered_workspace.restype = ctypes.c_size_t
+    L.sanns_slot_ranges.argtypes = [vp, vp, vp, u32, vp, u64, vp]
+    L.sanns_slot_ranges.restype = st
     L.sanns_kmeans_workspace.argtypes = [u32, u32]
     L.sanns_kmeans_workspace.restype = ctypes.c_size_t
     L.sanns_kmeans_init.argtypes = [vp, u64, u32, vp, u32, vp, vp, vp]
@@ -244,6 +246,11 @@ def sanns_distances_gathered(ctx: int, points: int, dtype: int, n: int, d: int,
 def sanns_distances_gathered_workspace(ctx: int, d: int, Q: int, M: int, tail=None) -> int:
     return load().sanns_distances_gathered_workspace(
         ctx, d, Q, M, None if tail is None else ctypes.byref(tail))
+
+
+def sanns_slot_ranges(start: int, length: int, off: int, R: int, slot_point: int, total: int,
+                      stream: int = 0) -> None:
+    _check(load().sanns_slot_ranges(start, length, off, R, slot_point, total, stream))
 
 
 def sanns_kmeans_workspace(k: int, d: int) -> int:

@@ -337,6 +337,7 @@ def test_clustered_full_size_gathered_phase2(cworld):
     (co, cs, slot, rq), _ = gsrv.point_distances_gathered(torch.as_tensor(ct_host).to(dev), qids,
                                                           W["selected"])
     torch.cuda.synchronize()
+    slot = slot.cpu().numpy()
     g = np.random.default_rng(94)
     js = sorted(set([0, N - 1] + [int(x) for x in g.integers(0, N, 16)]))
     last = int(np.nonzero(rq == Q - 1)[0][-1])

@@ -205,6 +205,9 @@ def test_clustered_gathered_phase2_equals_resident(mods):
     out, share, work = res.point_distances(ct, qids, selected)
     dres = dist_of(out, share, work[:, 0])
     (co, cs, slot, rq), (so, ss) = gat.point_distances_gathered(ct, qids, selected)
+    slot = slot.cpu().numpy()
+    hs, hq = gat.gather_plan(selected)  # the host plan gives the same map
+    assert (hs == slot).all() and (hq == rq).all()
     dgc = dist_of(co, cs, rq)
     dgs = dist_of(so, ss, np.repeat(np.arange(Q), gat.sdb.n_chunks))
     torch.cuda.synchronize()
