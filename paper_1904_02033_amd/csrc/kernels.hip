@@ -248,15 +248,34 @@ __device__ __forceinline__ void intt_mask_poly(int p, int tid, uint64_t* lds,
   for (int a = 0; a < 16; ++a) buf[coef_index<LOGN>(tid, a)] = v[a];
 }
 
+// The polynomial of ct_out that workgroup b of a grid of 8 ceil(n / 8) takes
+// (n = 2 L M polynomials; -1 for the grid's padding).  Consecutive blocks go
+// to the eight XCDs in turn, so block b is the (b / 8)-th of XCD b % 8, and
+// each XCD takes a contiguous range of this order: for all pairs (Qa > 0
+// queries, M = Qa C) chunk-major, the outputs of one chunk for every query
+// back to back, so that the chunk's norms are fetched once into that XCD's
+// L2; and the 2L polynomials of an output adjacent, so that the L that read
+// its mask row find it there.  A work list (Qa = 0) keeps its own order.
+__device__ __forceinline__ int intt_poly_of_block(int b, int n, int Qa, int C, int L) {
+  const int per = (n + 7) >> 3;
+  const int idx = (b & 7) * per + (b >> 3);
+  if (idx >= n) return -1;
+  if (Qa <= 0) return idx;
+  const int l = idx % L, c = (idx / L) & 1, r = idx / (2 * L);
+  return (((r % Qa) * C + r / Qa) * 2 + c) * L + l;
+}
+
 // At N = 8192: six waves per SIMD (78 registers, three workgroups of 512
 // threads per CU) run 8% faster than four (126 registers, two workgroups).
 template <int LOGN>
 __global__ void __launch_bounds__(NttShape<LOGN>::T, intt_mask_waves(LOGN))
 k_intt_mask(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
             const uint32_t* __restrict__ norms, const uint32_t* __restrict__ work, int C,
-            int L, uint32_t t, PrimeSet ps, TwSet tws) {
+            int L, uint32_t t, PrimeSet ps, TwSet tws, int n, int Qa) {
   extern __shared__ uint64_t lds[];
-  intt_mask_poly<LOGN>(blockIdx.x, threadIdx.x, lds, ct, share, norms, work, C, L, t, ps, tws);
+  const int p = intt_poly_of_block(blockIdx.x, n, Qa, C, L);
+  if (p < 0) return;
+  intt_mask_poly<LOGN>(p, threadIdx.x, lds, ct, share, norms, work, C, L, t, ps, tws);
 }
 
 // --------------------------------------------------------------------------
@@ -386,10 +405,11 @@ __global__ void __launch_bounds__(NttShape<LOGN>::T, intt_mask_waves(LOGN))
 k_intt_mask_cp(uint64_t* __restrict__ ct, const uint32_t* __restrict__ share,
                const uint32_t* __restrict__ norms, const uint32_t* __restrict__ work, int C,
                int L, uint32_t t, const uint64_t* __restrict__ flood,
-               const int8_t* __restrict__ errs, PrimeSet ps, TwSet tws) {
+               const int8_t* __restrict__ errs, PrimeSet ps, TwSet tws, int n, int Qa) {
   extern __shared__ uint64_t lds[];
   constexpr int N = NttShape<LOGN>::N;
-  const int tid = threadIdx.x, p = blockIdx.x;
+  const int tid = threadIdx.x, p = intt_poly_of_block(blockIdx.x, n, Qa, C, L);
+  if (p < 0) return;
   const int l = p % L, c = (p / L) & 1, m = p / (2 * L);
   const Prime& P = ps.p[l];
   uint64_t* buf = ct + (size_t)p * N;
@@ -1643,11 +1663,13 @@ hipError_t launch_intt_mask(uint64_t* ct, const uint32_t* share, const uint32_t*
                             const uint32_t* work, int C, int M, int logN, int L, uint32_t t,
                             const PrimeSet& ps, const TwSet& tws, hipStream_t st) {
   if (M <= 0) return hipSuccess;
+  const int n = M * 2 * L, Qa = work ? 0 : M / C;
+  const unsigned grid = (unsigned)((n + 7) / 8 * 8);
   switch (logN) {
 #define SANNS_CASE(LG)                                                                  \
   case LG:                                                                              \
-    ntt_launch<LG>(k_intt_mask<LG>, (unsigned)(M * 2 * L), st, ct, share, norms, work, C, \
-                   L, t, ps, tws);                                                      \
+    ntt_launch<LG>(k_intt_mask<LG>, grid, st, ct, share, norms, work, C, L, t, ps, tws, \
+                   n, Qa);                                                              \
     break;
     SANNS_LOGN_CASES(SANNS_CASE)
 #undef SANNS_CASE
@@ -1946,13 +1968,15 @@ hipError_t launch_intt_mask_cp(uint64_t* ct, const uint32_t* share, const uint32
   const int N = 1 << logN;
   const long nf = (long)M * (N / 2);
   int8_t* errs = reinterpret_cast<int8_t*>(flood + (size_t)M * L * N);
+  const int n = M * 2 * L, Qa = work ? 0 : M / C;
+  const unsigned grid = (unsigned)((n + 7) / 8 * 8);
   hipLaunchKernelGGL(k_cp_noise, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, K, qids,
                      work, C, (long)M, N, L, cp, ds, ps, flood, errs);
   switch (logN) {
 #define SANNS_CASE(LG)                                                                       \
   case LG:                                                                                   \
-    ntt_launch<LG>(k_intt_mask_cp<LG>, (unsigned)(M * 2 * L), st, ct, share, norms, work, C, L, \
-                   t, (const uint64_t*)flood, (const int8_t*)errs, ps, tws);                 \
+    ntt_launch<LG>(k_intt_mask_cp<LG>, grid, st, ct, share, norms, work, C, L, t,            \
+                   (const uint64_t*)flood, (const int8_t*)errs, ps, tws, n, Qa);              \
     break;
     SANNS_LOGN_CASES(SANNS_CASE)
 #undef SANNS_CASE
