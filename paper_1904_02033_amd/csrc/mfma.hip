@@ -44,16 +44,15 @@ constexpr int kMfmaChunks = 64;  // chunks per workgroup: 2 halves of 2 MFMA col
 constexpr int kMfmaSlots = 8;    // consecutive slots per workgroup
 constexpr int kDigitGroup = 32;  // slots per group of the query NTT form (form 2)
 constexpr int kQueryDigitSlots = 16;  // slots per workgroup of the query digit transpose
-// The database digit region ends with this many spare bytes: a staged half
-// tile may run past the last chunk (at most 32 chunks of at most 7 x 128 + 16
-// bytes each, plus one DMA round of 256 x 16 bytes).
+// The database digit region ends with this many spare bytes: a staged column
+// tile may run past the last chunk (k_mac_mfma checks the bound at compile
+// time).
 constexpr size_t kMfmaDbSlack = 64 * 1024;
 // s_waitcnt immediates (gfx9 encoding): vmcnt <= n (bits 3:0 and 15:14),
 // expcnt and lgkmcnt not waited for (7 in bits 6:4, 15 in bits 11:8).
 constexpr int vmcnt_wait(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
 constexpr int kWaitAllVmem = vmcnt_wait(0);
 constexpr int kWaitAllBut7Vmem = vmcnt_wait(7);
-constexpr int kWaitAllBut8Vmem = vmcnt_wait(8);
 constexpr int kWaitAllBut14Vmem = vmcnt_wait(14);
 
 // The signed digits of x < 2^54 as the bytes of a word (byte 7 is zero).
@@ -167,47 +166,6 @@ __device__ __forceinline__ uint64_t fold_digit_sums(const int32_t (&S)[13],
          shoup_approx(x2, D.w64, D.w64p, D.nq);  // < 2^55 + 8q < 2^58
 }
 
-// LDS byte address of a shared-memory pointer.
-__device__ __forceinline__ uint32_t lds_address(const void* p) {
-  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
-}
-
-// The 16-byte fragments of the 7 digit rows (DP bytes apart) of one column
-// tile and step, read in one asm block that waits for its own reads before
-// it ends (its outputs are never written behind the compiler's back).
-template <int DP>
-__device__ __forceinline__ void lds_frags(uint32_t addr, v4i (&bf)[7]) {
-  asm volatile(
-      "ds_read_b128 %0, %7\n\t"
-      "ds_read_b128 %1, %7 offset:%8\n\t"
-      "ds_read_b128 %2, %7 offset:%9\n\t"
-      "ds_read_b128 %3, %7 offset:%10\n\t"
-      "ds_read_b128 %4, %7 offset:%11\n\t"
-      "ds_read_b128 %5, %7 offset:%12\n\t"
-      "ds_read_b128 %6, %7 offset:%13\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(bf[0]), "=&v"(bf[1]), "=&v"(bf[2]), "=&v"(bf[3]), "=&v"(bf[4]), "=&v"(bf[5]),
-        "=&v"(bf[6])
-      : "v"(addr), "n"(DP), "n"(2 * DP), "n"(3 * DP), "n"(4 * DP), "n"(5 * DP), "n"(6 * DP));
-}
-
-// The same for a 32-coordinate step: 8-byte fragments.
-template <int DP>
-__device__ __forceinline__ void lds_frags(uint32_t addr, int64_t (&bf)[7]) {
-  asm volatile(
-      "ds_read_b64 %0, %7\n\t"
-      "ds_read_b64 %1, %7 offset:%8\n\t"
-      "ds_read_b64 %2, %7 offset:%9\n\t"
-      "ds_read_b64 %3, %7 offset:%10\n\t"
-      "ds_read_b64 %4, %7 offset:%11\n\t"
-      "ds_read_b64 %5, %7 offset:%12\n\t"
-      "ds_read_b64 %6, %7 offset:%13\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(bf[0]), "=&v"(bf[1]), "=&v"(bf[2]), "=&v"(bf[3]), "=&v"(bf[4]), "=&v"(bf[5]),
-        "=&v"(bf[6])
-      : "v"(addr), "n"(DP), "n"(2 * DP), "n"(3 * DP), "n"(4 * DP), "n"(5 * DP), "n"(6 * DP));
-}
-
 // One MFMA step of the contraction: 64 coordinates (16 bytes per lane,
 // v_mfma_i32_16x16x64_i8) or 32 (8 bytes per lane, v_mfma_i32_16x16x32_i8,
 // lane l supplying row or column l % 16 and contraction bytes 8 (l / 16) ..
@@ -230,37 +188,40 @@ __device__ __forceinline__ v4i mfma_digits(typename StepFrag<W32>::T a,
 }
 
 // One workgroup: 64 rows x 64 chunks of kMfmaSlots consecutive slots of one
-// limb, the chunks taken as two halves of 32 that reuse the same query
-// fragments.  Wave w owns rows 16w .. 16w + 15 of the tile and the two
-// 16-chunk column tiles of the current half; its query fragments come
-// straight from global memory into registers, the half's database digits are
-// staged in LDS by DMA (global_load_lds): a slot's first half in sb0, its
-// second in sb1.  The DMA into one buffer is issued at the start of the half
-// that multiplies the other, so it lands behind that half's MFMAs.  Every memory
-// operation of the slot loop is unconditional (the digit region has slack
-// past its end, the sums buffer is padded to whole tiles), so the loop body is
-// straight-line code whose memory counters the compiler tracks exactly.
-// Query fragments are loaded one step ahead during the second half: those of
-// the next slot's first step while this slot's second step is multiplied,
-// those of its second step while the sums are folded.  Before each barrier
-// that publishes a buffer, a counted wait retires this wave's DMA into it
-// (and nothing newer); the stores go out after the barrier.  Workgroups are
-// numbered so that the tiles of one slot range run back to back on one XCD,
-// which shares the operands in its L2.
+// limb.  Wave w owns rows 16w .. 16w + 15 of the tile; its query fragments
+// come straight from global memory into registers and serve the four
+// 16-chunk column tiles of a slot.  The database digits are staged in LDS by
+// DMA (global_load_lds) one column tile (stage) at a time, double-buffered
+// in 2 x 16 KB, so that three workgroups fit on a CU (three waves per SIMD,
+// at most 168 registers each; two workgroups of 32-chunk stages at 256
+// registers ran 4-5% slower).  The DMA of the next stage is issued at the
+// start of a stage, so it lands behind that stage's MFMAs (49 per
+// 64-coordinate step), fold and stores.  Every memory operation of the loop is
+// unconditional (the digit region has slack past its end, the sums buffer is
+// padded to whole tiles): a stage's DMA may run up to 65 chunks past the last
+// one (16 KB of reads from at most 47 chunks past it).  The query fragments
+// of the next slot are loaded during the last stage of a slot, behind its
+// MFMAs.  Before each barrier that publishes a buffer, a counted wait retires
+// this wave's DMA into it (and nothing newer); the stores go out after the
+// barrier.  The database fragments are plain LDS loads, which the compiler
+// issues ahead of their MFMAs; empty asm statements with a memory clobber
+// around each barrier keep them behind it.  Workgroups are numbered so that
+// the tiles of one slot range run back to back on one XCD, which shares the
+// operands in its L2.
 template <int DP>
-__global__ void __launch_bounds__(256, 2)
+__global__ void __launch_bounds__(256, 3)
 k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R, int C, int L,
-           int logN, int n_items, DigitSet ds, uint64_t* __restrict__ sums) {
+             int logN, int n_items, DigitSet ds, uint64_t* __restrict__ sums) {
   constexpr int Dp = DP, Sk = 7 * Dp + 16, Dq = (Dp + 63) / 64 * 64;
-  // steps of the contraction: one or two; step 0 is 32 coordinates wide when
-  // Dp = 32, step 1 when Dp = 96, every other step 64
   constexpr int NS = (Dp + 63) / 64;
   constexpr bool W0 = Dp < 64, W1 = Dp % 64 != 0;
   typedef typename StepFrag<W0>::T F0;
   typedef typename StepFrag<W1>::T F1;
-  constexpr int H = kMfmaChunks / 2;        // chunks per half
-  constexpr int BU = H * Sk / 16;           // 16-byte units of one staged half
-  constexpr int BR = (BU + 255) / 256;      // DMA rounds of the 256 threads
+  constexpr int H = 16;                 // chunks per stage
+  constexpr int BU = H * Sk / 16;       // 16-byte units of one stage
+  constexpr int BR = (BU + 255) / 256;  // DMA rounds of the 256 threads
+  static_assert(BR * 256 * 16 + (kMfmaChunks - H) * Sk <= (int)kMfmaDbSlack,
+                "a stage's DMA stays inside the digit region's slack");
   __shared__ uint4 sb0[BR * 256], sb1[BR * 256];
   const int N = 1 << logN;
   const int per_xcd = (n_items + 7) >> 3;
@@ -277,20 +238,15 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
   const int wrow0 = rt * kMfmaRows + 16 * w;
   const int arow = wrow0 + m16 < R ? wrow0 + m16 : R - 1;
   const DigitConst& D = ds.c[l];
-  // DMA of half h of slot p's database tile into buf.  Units past the last
-  // chunk read the following bytes of the digit region (the next slot's
-  // chunks, or the region's slack of kMfmaDbSlack bytes at its end): data in
-  // rows whose sums nobody reads.
-  auto stage = [&](int p, int h, uint4* buf) {
+  auto stage = [&](int p, int cq, uint4* buf) {
     const uint4* src = reinterpret_cast<const uint4*>(
-        dbd + (((size_t)l * N + p) * C + k0 + h * H) * Sk);
+        dbd + (((size_t)l * N + p) * C + k0 + cq * H) * Sk);
 #pragma unroll
     for (int m = 0; m < BR; ++m)
       __builtin_amdgcn_global_load_lds(
           (const void*)(src + tid + 256 * m),
           (__attribute__((address_space(3))) void*)(buf + 256 * m + 64 * w), 16, 0, 0);
   };
-  // Query fragments of step ks of slot p.
   auto load_a = [&](int p, int ks, auto (&af)[7]) {
     typedef typename std::remove_reference<decltype(af[0])>::type F;
     const int8_t* ab = qd + (((size_t)l * N + p) * R + arow) * (size_t)(7 * Dq) +
@@ -298,54 +254,84 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
 #pragma unroll
     for (int a = 0; a < 7; ++a) af[a] = *reinterpret_cast<const F*>(ab + a * Dq);
   };
-  // 98 MFMAs of one step: every digit pair (a, b) of both column tiles into
-  // diagonal a + b; the first product of a diagonal starts from a zero
-  // accumulator (b = 0, or a = 6 for the diagonals above 6).
-  // The 7 database fragments of a column tile are read by lds_frags (one
-  // asm block with its own wait: the compiler, which cannot tell the two
-  // staging buffers apart, would otherwise hold every LDS read until a DMA
-  // into the other buffer has landed).
-  // The lane's byte offset in a staged chunk row is sizeof(fragment) g.
-  auto mfma_step = [&](const auto (&af)[7], int ks, uint32_t buf, v4i (&acc)[2][13]) {
+  // 49 MFMAs of one step against the stage's column tile; the fragments are
+  // plain LDS loads, which the compiler issues ahead of their MFMAs (the asm
+  // clobbers at the barriers keep them after the barrier that publishes the
+  // buffer)
+  auto mfma_step = [&](const auto (&af)[7], int ks, const uint4* buf, v4i (&acc)[13]) {
     typedef typename std::remove_const<
         typename std::remove_reference<decltype(af[0])>::type>::type F;
     constexpr bool W = sizeof(F) == 8;
+    const char* fb = reinterpret_cast<const char*>(buf) + m16 * Sk + (int)sizeof(F) * g + 64 * ks;
 #pragma unroll
-    for (int cs = 0; cs < 2; ++cs) {
-      F bf[7];
-      lds_frags<Dp>(buf + m16 * Sk + (int)sizeof(F) * g + cs * 16 * Sk + 64 * ks, bf);
+    for (int b = 0; b < 7; ++b) {
+      const F bf = *reinterpret_cast<const F*>(fb + b * Dp);
 #pragma unroll
-      for (int b = 0; b < 7; ++b)
-#pragma unroll
-        for (int a = 0; a < 7; ++a)
-          acc[cs][a + b] = mfma_digits<W>(
-              af[a], bf[b], (ks == 0 && (b == 0 || a == 6)) ? v4i{0, 0, 0, 0} : acc[cs][a + b]);
+      for (int a = 0; a < 7; ++a)
+        acc[a + b] = mfma_digits<W>(
+            af[a], bf, (ks == 0 && (b == 0 || a == 6)) ? v4i{0, 0, 0, 0} : acc[a + b]);
     }
   };
-  // Fold of the accumulators of one half into sums below 2^58.
-  auto fold = [&](const v4i (&acc)[2][13], uint64_t (&v)[2][4]) {
-#pragma unroll
-    for (int cs = 0; cs < 2; ++cs)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int32_t S[13];
-#pragma unroll
-        for (int s = 0; s < 13; ++s) S[s] = acc[cs][s][e];
-        v[cs][e] = fold_digit_sums(S, D);
+  // one stage: quarter cq of slot p from buf, the next stage's DMA into nxt
+  auto run_stage = [&](int p, int cq, const uint4* buf, uint4* nxt, int pn, F0 (&a0)[7],
+                       F1 (&a1)[7]) {
+    if (cq == 0) {
+      // the slot's step-0 fragments: older than the step-1 loads (NS == 2)
+      // and the previous stage's 4 stores
+      __builtin_amdgcn_s_waitcnt(vmcnt_wait(NS == 2 ? 11 : 4));
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (cq < 3)
+      stage(p, cq + 1, nxt);
+    else
+      stage(pn, 0, nxt);
+    __builtin_amdgcn_sched_barrier(0);
+    v4i acc[13];
+    mfma_step(a0, 0, buf, acc);
+    if constexpr (NS == 2) {
+      if (cq == 0) {
+        // the step-1 fragments: older than the stores and this stage's DMA
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(vmcnt_wait(4 + BR));
       }
-  };
-  // lane holds rows 4g .. 4g + 3 of the wave's 16, chunk m16 of each column tile
-  auto store = [&](int p, int h, const uint64_t (&v)[2][4]) {
-    uint64_t* dst =
-        sums + (((size_t)l * N + p) * Rp + wrow0 + 4 * g) * Cp + k0 + h * H + m16;
+      if (cq == 3) {
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(pn, 0, a0);  // the next slot's step-0 fragments, behind step 1
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_step(a1, 1, buf, acc);
+      if (cq == 3) {
+        __builtin_amdgcn_sched_barrier(0);
+        load_a(pn, 1, a1);
+      }
+    } else if (cq == 3) {
+      __builtin_amdgcn_sched_barrier(0);
+      load_a(pn, 0, a0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    uint64_t v[4];
 #pragma unroll
-    for (int cs = 0; cs < 2; ++cs)
+    for (int e = 0; e < 4; ++e) {
+      int32_t S[13];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) dst[(size_t)e * Cp + 16 * cs] = v[cs][e];
+      for (int s2 = 0; s2 < 13; ++s2) S[s2] = acc[s2][e];
+      v[e] = fold_digit_sums(S, D);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    // the DMA into nxt: older than the fragment loads of a last stage
+    if (cq == 3)
+      __builtin_amdgcn_s_waitcnt(NS == 2 ? kWaitAllBut14Vmem : kWaitAllBut7Vmem);
+    else
+      __builtin_amdgcn_s_waitcnt(kWaitAllVmem);
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    uint64_t* dst = sums + (((size_t)l * N + p) * Rp + wrow0 + 4 * g) * Cp + k0 + cq * H + m16;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dst[(size_t)e * Cp] = v[e];
   };
 
-  const uint32_t b0 = lds_address(sb0);
-  const uint32_t b1 = lds_address(sb1);
   F0 a0[7];
   F1 a1[7];
   stage(p0, 0, sb0);
@@ -355,50 +341,11 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
   __syncthreads();
   for (int jj = 0; jj < kMfmaSlots; ++jj) {
     const int p = p0 + jj;
-    // the last slot restages itself (keeps the body uniform)
-    const int pn = jj + 1 < kMfmaSlots ? p + 1 : p;
-    uint64_t v[2][4];
-    {  // first half: chunks k0 .. k0 + 31 from sb0, the second half's DMA into sb1
-      // the slot's query fragments (older than the previous half's 8 stores)
-      __builtin_amdgcn_s_waitcnt(kWaitAllBut8Vmem);
-      __builtin_amdgcn_sched_barrier(0);
-      stage(p, 1, sb1);
-      __builtin_amdgcn_sched_barrier(0);
-      v4i acc[2][13];
-      mfma_step(a0, 0, b0, acc);
-      if constexpr (NS == 2) mfma_step(a1, 1, b0, acc);
-      __builtin_amdgcn_sched_barrier(0);
-      fold(acc, v);
-      __builtin_amdgcn_sched_barrier(0);
-      __builtin_amdgcn_s_waitcnt(kWaitAllVmem);  // the DMA into sb1
-      __builtin_amdgcn_sched_barrier(0);
-      __builtin_amdgcn_s_barrier();
-      store(p, 0, v);
-    }
-    {  // second half from sb1, the next slot's first half into sb0, its fragments
-      stage(pn, 0, sb0);
-      __builtin_amdgcn_sched_barrier(0);
-      v4i acc[2][13];
-      mfma_step(a0, 0, b1, acc);
-      __builtin_amdgcn_sched_barrier(0);
-      if constexpr (NS == 2) {
-        load_a(pn, 0, a0);  // step 0 of the next slot, during this step 1
-        __builtin_amdgcn_sched_barrier(0);
-        mfma_step(a1, 1, b1, acc);
-        __builtin_amdgcn_sched_barrier(0);
-        load_a(pn, 1, a1);  // step 1 of the next slot, during the fold
-      } else {
-        load_a(pn, 0, a0);
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      fold(acc, v);
-      __builtin_amdgcn_sched_barrier(0);
-      // the DMA into sb0 (older than the newest 7 fragment loads per step)
-      __builtin_amdgcn_s_waitcnt(NS == 2 ? kWaitAllBut14Vmem : kWaitAllBut7Vmem);
-      __builtin_amdgcn_sched_barrier(0);
-      __builtin_amdgcn_s_barrier();
-      store(p, 1, v);
-    }
+    const int pn = jj + 1 < kMfmaSlots ? p + 1 : p;  // the last slot restages itself
+    run_stage(p, 0, sb0, sb1, pn, a0, a1);
+    run_stage(p, 1, sb1, sb0, pn, a0, a1);
+    run_stage(p, 2, sb0, sb1, pn, a0, a1);
+    run_stage(p, 3, sb1, sb0, pn, a0, a1);
   }
 }
 
