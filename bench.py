@@ -49,7 +49,7 @@ def device_source_hash() -> str:
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in ["kernels.hip", "mfma.hip", "kernels.h", "modarith.h", "ntt.h"]:
+    for f in ["kernels.hip", "mfma.hip", "kernels.h", "modarith.h", "ntt.h", "chacha.h"]:
         with open(os.path.join(ROOT, "paper_1904_02033_amd", "csrc", f)) as fh:
             text = re.sub(r"//[^\n]*", "", fh.read())
         h.update(" ".join(text.split()).encode())

@@ -493,13 +493,16 @@ sanns_status sanns_set_schedule(sanns_ctx *ctx, int lds_variant, int qt, int ct)
 
 /* Phases timed by the profiler, in launch order. */
 #define SANNS_PHASE_QUERY_NTT 0 /* forward NTT of the query ciphertexts     */
-#define SANNS_PHASE_MASKS 1     /* ChaCha20 masks -> server shares          */
+#define SANNS_PHASE_MASKS 1     /* ChaCha20 masks -> server shares (drawn
+                                   inside SANNS_PHASE_SUMS by the matrix-core
+                                   schedule: 0 there)                       */
 #define SANNS_PHASE_MAC 2       /* multiply-accumulate over the database    */
 #define SANNS_PHASE_INTT_MASK 3 /* INTT + Delta [||p||^2 - r]_t             */
 #define SANNS_PHASE_DIGITS 4    /* SANNS_SCHEDULE_MFMA: query NTT form ->
                                    signed digits (0 for other schedules)    */
 #define SANNS_PHASE_SUMS 5      /* SANNS_SCHEDULE_MFMA: slot-major sums ->
-                                   NTT-form outputs (0 for other schedules) */
+                                   NTT-form outputs, and the masks (0 for
+                                   other schedules)                         */
 #define SANNS_PHASE_RERAND 6    /* sanns_distances_cp: public keys' NTT and
                                    u pk added to the NTT-form outputs       */
 #define SANNS_N_PHASES 7

@@ -98,9 +98,12 @@ hipError_t launch_db_digits(const uint2* dbres, int8_t* dbd, int C, int d, int L
 size_t mfma_sums_bytes(int Q, int C, int L, int logN);
 hipError_t launch_mac_mfma(const int8_t* qd, const int8_t* dbd, int Q, int d, int C, int L,
                            int logN, const DigitSet& ds, uint64_t* sums, hipStream_t st);
-// The sums reduced to [0, q) and transposed into ct_out [Q C][2][L][N] (NTT form).
+// The sums reduced to [0, q) and transposed into ct_out [Q C][2][L][N] (NTT
+// form); with share != NULL the same launch writes the server masks of the
+// Q C outputs (output m = q C + k), as launch_masks does.
 hipError_t launch_sums_to_ct(const uint64_t* sums, uint64_t* ct_out, int Q, int C, int L,
-                             int logN, const PrimeSet& ps, hipStream_t st);
+                             int logN, const PrimeSet& ps, hipStream_t st, const MaskKey& K,
+                             const uint64_t* qids, uint32_t t, uint64_t tone, uint32_t* share);
 
 hipError_t launch_gather(const void* pts, int is_signed, long n, int d,
                          const int64_t* slot_point, long base, long total, int logN,

@@ -33,6 +33,7 @@
 #include <type_traits>
 #include "kernels.h"
 #include "launch.h"
+#include "chacha.h"
 
 namespace sanns {
 
@@ -351,11 +352,18 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
 
 // Slot-major sums [L][N][Rp][Cp] (values below 2^58) -> ciphertexts
 // [Q C][2][L][N] reduced to [0, q) (output m = q C + k, component c = row & 1):
-// 64 slots x 32 chunks of one row per workgroup.
+// 64 slots x 32 chunks of one row per workgroup.  The same launch draws the
+// server masks of all Q C outputs (share != NULL): the ALU work of ChaCha20
+// runs while this memory-bound transpose waits for its loads.  Mask blocks
+// (four slots each, N / 4 per output) go in jobs of 64 consecutive blocks to
+// whole waves: job j to wave j / gridDim.x of workgroup j mod gridDim.x (at
+// most 4 jobs per workgroup, since there are at most C / (8 L ceil(C / 32))
+// per workgroup).
 __global__ void __launch_bounds__(256)
 k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R, int C, int L,
-             int logN, PrimeSet ps) {
-  __shared__ uint64_t t[32][65];
+             int logN, PrimeSet ps, MaskKey K, const uint64_t* __restrict__ qids, uint32_t t,
+             uint64_t tone, uint32_t* __restrict__ share) {
+  __shared__ uint64_t tb[32][65];
   const int N = 1 << logN;
   const int ng = N / 64, nkg = (C + 31) / 32;
   int b = blockIdx.x;
@@ -368,9 +376,25 @@ k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R
   const int tid = threadIdx.x;
   const int Rp = (R + kMfmaRows - 1) / kMfmaRows * kMfmaRows;
   const int Cp = (C + kMfmaChunks - 1) / kMfmaChunks * kMfmaChunks;
-  for (int idx = tid; idx < 64 * 32; idx += 256) {
-    const int kk = idx % 32, pp = idx / 32;
-    if (k0 + kk < C) t[kk][pp] = sums[(((size_t)l * N + p0 + pp) * Rp + row) * Cp + k0 + kk];
+  uint64_t x[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int idx = tid + 256 * i, kk = idx % 32, pp = idx / 32;
+    x[i] = k0 + kk < C ? sums[(((size_t)l * N + p0 + pp) * Rp + row) * Cp + k0 + kk] : 0;
+  }
+  if (share) {
+    const int nb = N >> 2;
+    const long n_blocks = (long)(R >> 1) * C * nb;
+    const long blk = ((long)blockIdx.x + (long)(tid >> 6) * gridDim.x) * 64 + (tid & 63);
+    if (blk < n_blocks) {
+      const int m = (int)(blk / nb), bb = (int)(blk % nb);
+      mask_block(K, qids[m / C], m % C, bb, t, tone, share + (size_t)m * N);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int idx = tid + 256 * i, kk = idx % 32, pp = idx / 32;
+    tb[kk][pp] = x[i];
   }
   __syncthreads();
   const int q = row >> 1, c = row & 1;
@@ -379,7 +403,7 @@ k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R
   for (int idx = tid; idx < 64 * 32; idx += 256) {
     const int pp = idx % 64, kk = idx / 64;
     if (k0 + kk < C) {
-      const uint64_t r = shoup_approx(t[kk][pp], 1, P.one, nq);  // [0, 4q)
+      const uint64_t r = shoup_approx(tb[kk][pp], 1, P.one, nq);  // [0, 4q)
       ct[((((size_t)q * C + k0 + kk) * 2 + c) * L + l) * N + p0 + pp] =
           csub(csub(r, 2 * P.q), P.q);
     }
@@ -456,13 +480,16 @@ hipError_t launch_mac_mfma(const int8_t* qd, const int8_t* dbd, int Q, int d, in
 }
 
 hipError_t launch_sums_to_ct(const uint64_t* sums, uint64_t* ct_out, int Q, int C, int L,
-                             int logN, const PrimeSet& ps, hipStream_t st) {
+                             int logN, const PrimeSet& ps, hipStream_t st, const MaskKey& K,
+                             const uint64_t* qids, uint32_t t, uint64_t tone, uint32_t* share) {
   if (logN < 6) return hipErrorInvalidValue;
   if (Q <= 0 || C <= 0) return hipSuccess;
   const int R = 2 * Q, N = 1 << logN;
   const long nb = (long)L * (N / 64) * R * ((C + 31) / 32);
+  // the mask jobs must fit in the workgroups' four waves
+  if (share && ((long)Q * C * (N / 4) + 63) / 64 > 4 * nb) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sums_to_ct, dim3((unsigned)nb), dim3(256), 0, st, sums, ct_out, R, C, L,
-                     logN, ps);
+                     logN, ps, K, qids, t, tone, share);
   return hipGetLastError();
 }
 

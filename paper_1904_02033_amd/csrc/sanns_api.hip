@@ -742,8 +742,9 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
     HIP_TRY(launch_query_digits(qntt, qdig, (int)Q, (int)d, (int)L, ctx->logN, st));
   HIP_TRY(mark(SANNS_PHASE_DIGITS, true));
   HIP_TRY(mark(SANNS_PHASE_MASKS, false));
-  HIP_TRY(launch_masks(K, qids, dwork, (int)C, (int)M, ctx->logN, (uint32_t)ctx->p.t, ctx->tone,
-                       share, st));
+  if (!mfma)  // the matrix-core schedule draws them in its sums transpose
+    HIP_TRY(launch_masks(K, qids, dwork, (int)C, (int)M, ctx->logN, (uint32_t)ctx->p.t,
+                         ctx->tone, share, st));
   HIP_TRY(mark(SANNS_PHASE_MASKS, true));
   HIP_TRY(mark(SANNS_PHASE_MAC, false));
   if (mfma) {
@@ -759,7 +760,8 @@ sanns_status enqueue_fused(sanns_ctx* ctx, const sanns_db* db, const uint64_t* c
   HIP_TRY(mark(SANNS_PHASE_MAC, true));
   HIP_TRY(mark(SANNS_PHASE_SUMS, false));
   if (mfma)
-    HIP_TRY(launch_sums_to_ct(sums, ct_out, (int)Q, (int)C, (int)L, ctx->logN, ctx->ps, st));
+    HIP_TRY(launch_sums_to_ct(sums, ct_out, (int)Q, (int)C, (int)L, ctx->logN, ctx->ps, st, K,
+                              qids, (uint32_t)ctx->p.t, ctx->tone, share));
   HIP_TRY(mark(SANNS_PHASE_SUMS, true));
   HIP_TRY(mark(SANNS_PHASE_RERAND, false));
   if (cp.on) {
