@@ -330,7 +330,7 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
     asm volatile("" ::: "memory");
     uint64_t* dst = sums + (((size_t)l * N + p) * Rp + wrow0 + 4 * g) * Cp + k0 + cq * H + m16;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) dst[(size_t)e * Cp] = v[e];
+    for (int e = 0; e < 4; ++e) __builtin_nontemporal_store(v[e], dst + (size_t)e * Cp);
   };
 
   F0 a0[7];
