@@ -58,7 +58,7 @@ __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
   bool bad = false;
 #pragma unroll
   for (int a = 0; a < 16; ++a) {
-    v[a] = src[coef_index<LOGN>(tid, a)];
+    v[a] = __builtin_nontemporal_load(src + coef_index<LOGN>(tid, a));  // read once
     bad |= v[a] >= P.q;
   }
   if (bad && err) atomicOr(err, 1u);
@@ -175,7 +175,7 @@ __device__ __forceinline__ void intt_mask_poly(int p, int tid, uint64_t* lds,
   uint64_t* buf = ct + (size_t)p * N;
   uint64_t v[16];
 #pragma unroll
-  for (int a = 0; a < 16; ++a) v[a] = buf[ntt_slot<LOGN>(tid, a)];
+  for (int a = 0; a < 16; ++a) v[a] = __builtin_nontemporal_load(buf + ntt_slot<LOGN>(tid, a));
   ntt_inv<LOGN>(v, lds, tid, tws.tw[l] + N, P);
   if (c == 0) {
     int qi, k;
@@ -192,7 +192,7 @@ __device__ __forceinline__ void intt_mask_poly(int p, int tid, uint64_t* lds,
   }
   __syncthreads();  // every thread has read its inputs before any overwrite
 #pragma unroll
-  for (int a = 0; a < 16; ++a) buf[coef_index<LOGN>(tid, a)] = v[a];
+  for (int a = 0; a < 16; ++a) __builtin_nontemporal_store(v[a], buf + coef_index<LOGN>(tid, a));
 }
 
 // The polynomial of ct_out that workgroup b of a grid of 8 ceil(n / 8) takes

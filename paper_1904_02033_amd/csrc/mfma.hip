@@ -380,7 +380,9 @@ k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int idx = tid + 256 * i, kk = idx % 32, pp = idx / 32;
-    x[i] = k0 + kk < C ? sums[(((size_t)l * N + p0 + pp) * Rp + row) * Cp + k0 + kk] : 0;
+    x[i] = k0 + kk < C ? __builtin_nontemporal_load(
+                             sums + (((size_t)l * N + p0 + pp) * Rp + row) * Cp + k0 + kk)
+                       : 0;
   }
   if (share) {
     const int nb = N >> 2;
@@ -404,8 +406,8 @@ k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R
     const int pp = idx % 64, kk = idx / 64;
     if (k0 + kk < C) {
       const uint64_t r = shoup_approx(tb[kk][pp], 1, P.one, nq);  // [0, 4q)
-      ct[((((size_t)q * C + k0 + kk) * 2 + c) * L + l) * N + p0 + pp] =
-          csub(csub(r, 2 * P.q), P.q);
+      __builtin_nontemporal_store(csub(csub(r, 2 * P.q), P.q),
+                                  ct + ((((size_t)q * C + k0 + kk) * 2 + c) * L + l) * N + p0 + pp);
     }
   }
 }
