@@ -41,7 +41,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr uint64_t kDigitBias = 0x0080808080808080ull;  // 128 in each of bytes 0..6
 constexpr int kMfmaRows = 64;    // rows per workgroup: 4 waves x 16
-constexpr int kMfmaChunks = 64;  // chunks per workgroup: 2 halves of 2 MFMA column tiles
+constexpr int kMfmaChunks = 64;  // chunks per workgroup: 4 stages of one 16-chunk MFMA column tile
 constexpr int kMfmaSlots = 8;    // consecutive slots per workgroup
 constexpr int kDigitGroup = 32;  // slots per group of the query NTT form (form 2)
 constexpr int kQueryDigitSlots = 16;  // slots per workgroup of the query digit transpose
