@@ -128,6 +128,9 @@ def main():
                     choices=["batched-1Mx128", "batched-1Mx96", "linear-10Kx128",
                              "clustered-10M", "serving", "balance-1Mx96"])
     ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-budget-gib", type=float, default=0.0,
+                    help="HBM budget of the serving loop's request buffers "
+                         "(0: 75%% of the device memory free once the databases are resident)")
     ap.add_argument("--balance-m", type=int, default=22,
                     help="balance-1Mx96: largest cluster size m (the paper's Deep1B-1M value)")
     ap.add_argument("--balance-alpha", type=float, default=0.5)
@@ -716,6 +719,13 @@ def run_serving(args):
            serve.ResidentDB("C", ctxB, server=srv, u=64)]
     n_of = {"A": len(ptsA), "B": len(ptsB)}
     select = client_select_fn(srv, skB, lambda r: qB[r.pool_rows], 64)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if args.serving_budget_gib > 0:
+        budget = int(args.serving_budget_gib * (1 << 30))
+    else:
+        budget = int(0.75 * torch.cuda.mem_get_info(dev)[0])
+    log(f"serving budget {budget / (1 << 30):.1f} GiB for request buffers")
 
     def make_requests(rate, count, seed, per_query=False):
         """Requests of the arrival trace; with per_query every request is
@@ -743,7 +753,7 @@ def run_serving(args):
         # push the caching allocator into a synchronising retry in the next
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
-        s = serve.Server(dbs, hbm_budget=64 << 30, max_inflight=inflight,
+        s = serve.Server(dbs, hbm_budget=budget, max_inflight=inflight,
                          max_batch_queries=max_batch, client_select=select,
                          keep_outputs=False)
         t0 = time.perf_counter()
@@ -793,7 +803,8 @@ def run_serving(args):
         "config": {"workload": "serving: Poisson arrivals, Q ~ U{1..64}, k in {1,10,100}, "
                                "databases 100K x 128 uint8, 1M x 96 int8, clustered 10M x 96 "
                                "int8 (64 clusters per query); fused batched launches, "
-                               "3 in flight, <= 64 queries per launch"},
+                               "3 in flight, <= 64 queries per launch",
+                   "hbm_budget_gib": round(budget / (1 << 30), 1)},
         "latency": {"p50_ms_rho_0.9": out["rho_0.9"]["p50_ms"],
                     "p99_ms_rho_0.9": out["rho_0.9"]["p99_ms"],
                     "p50_ms_rho_0.5": out["rho_0.5"]["p50_ms"],

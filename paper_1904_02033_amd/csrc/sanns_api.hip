@@ -296,11 +296,14 @@ sanns_status stage_upload(sanns_ctx* ctx, void* dst, const void* src, size_t byt
   sanns_ctx::Staging& S = ctx->staging[pick];
   ctx->staging_next = (pick + 1) % K;
   if (bytes > S.bytes) {
+    // geometric growth: freeing pinned memory waits for the whole device, so
+    // a buffer is replaced a handful of times per context, not per size
+    const size_t cap = std::max({bytes, 2 * S.bytes, (size_t)1 << 20});
     if (S.buf) HIP_TRY(hipHostFree(S.buf));
     S.buf = nullptr;
     S.bytes = 0;
-    HIP_TRY(hipHostMalloc(&S.buf, bytes, hipHostMallocDefault));
-    S.bytes = bytes;
+    HIP_TRY(hipHostMalloc(&S.buf, cap, hipHostMallocDefault));
+    S.bytes = cap;
   }
   std::memcpy(S.buf, src, bytes);
   HIP_TRY(hipMemcpyAsync(dst, S.buf, bytes, hipMemcpyHostToDevice, st));

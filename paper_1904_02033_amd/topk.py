@@ -38,9 +38,19 @@ def naive_topk(values: np.ndarray, ids: np.ndarray, k: int) -> Tuple[np.ndarray,
     ids = np.asarray(ids, dtype=np.int64)
     out_v = np.full(k, np.iinfo(np.int64).max, dtype=np.int64)
     out_i = np.full(k, -1, dtype=np.int64)
-    kk = min(k, len(values))
+    n = len(values)
+    kk = min(k, n)
     if kk:
-        o = np.argsort(values, kind="stable")[:kk]
+        if kk < n:
+            # the k-th smallest value in linear time; every smaller value, then
+            # the first of the equal ones in input order
+            thr = np.partition(values, kk - 1)[kk - 1]
+            below = np.flatnonzero(values < thr)
+            eq = np.flatnonzero(values == thr)[:kk - len(below)]
+            sel = np.sort(np.concatenate([below, eq]))
+        else:
+            sel = np.arange(n)
+        o = sel[np.argsort(values[sel], kind="stable")]
         out_v[:kk], out_i[:kk] = values[o], ids[o]
     return out_v, out_i
 
