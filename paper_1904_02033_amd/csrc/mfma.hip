@@ -92,24 +92,34 @@ k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, i
   const int ent = b % n_ent, l = b / n_ent;
   const int p0 = pg * S;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < Dp * S; idx += NT) {
-    const int i = idx / S, pp = idx % S;
-    uint64_t x = 0;
-    if (i < d) {
-      if (DB) {
+  if constexpr (DB) {
+    for (int idx = tid; idx < Dp * S; idx += NT) {
+      const int i = idx / S, pp = idx % S;
+      uint64_t x = 0;
+      if (i < d) {
         const uint2 h = reinterpret_cast<const uint2*>(
             src)[(((size_t)l * C + ent) * d + i) * N + p0 + pp];
         x = (uint64_t)h.x + ((uint64_t)h.y << 27);
-      } else {
+      }
+      lw[i * P1 + pp] = digit_word(x);
+    }
+  } else {
+    // two consecutive slots of a coordinate per 16-byte load
+    typedef uint64_t u64x2v __attribute__((ext_vector_type(2)));
+    for (int idx = tid; idx < Dp * S / 2; idx += NT) {
+      const int i = idx / (S / 2), pp = 2 * (idx % (S / 2));
+      u64x2v x = {0, 0};
+      if (i < d) {
         const int pq = p0 + pp;
-        x = __builtin_nontemporal_load(
+        x = __builtin_nontemporal_load(reinterpret_cast<const u64x2v*>(
             reinterpret_cast<const uint64_t*>(src) +
             ((((size_t)l * n_ent + ent) * (N / kDigitGroup) + pq / kDigitGroup) * d + i) *
                 kDigitGroup +
-            pq % kDigitGroup);
+            pq % kDigitGroup));
       }
+      lw[i * P1 + pp] = digit_word(x.x);
+      lw[i * P1 + pp + 1] = digit_word(x.y);
     }
-    lw[i * P1 + pp] = digit_word(x);
   }
   __syncthreads();
   const int cg_n = Dp / 16;
@@ -376,13 +386,14 @@ k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R
   const int tid = threadIdx.x;
   const int Rp = (R + kMfmaRows - 1) / kMfmaRows * kMfmaRows;
   const int Cp = (C + kMfmaChunks - 1) / kMfmaChunks * kMfmaChunks;
-  uint64_t x[8];
+  // two consecutive chunks of a slot per 16-byte load (Cp is a multiple of 64)
+  typedef uint64_t u64x2v __attribute__((ext_vector_type(2)));
+  u64x2v x[4];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int idx = tid + 256 * i, kk = idx % 32, pp = idx / 32;
-    x[i] = k0 + kk < C ? __builtin_nontemporal_load(
-                             sums + (((size_t)l * N + p0 + pp) * Rp + row) * Cp + k0 + kk)
-                       : 0;
+  for (int i = 0; i < 4; ++i) {
+    const int idx = tid + 256 * i, kk = 2 * (idx % 16), pp = idx / 16;
+    x[i] = __builtin_nontemporal_load(reinterpret_cast<const u64x2v*>(
+        sums + (((size_t)l * N + p0 + pp) * Rp + row) * Cp + k0 + kk));
   }
   if (share) {
     const int nb = N >> 2;
@@ -394,20 +405,25 @@ k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R
     }
   }
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    const int idx = tid + 256 * i, kk = idx % 32, pp = idx / 32;
-    tb[kk][pp] = x[i];
+  for (int i = 0; i < 4; ++i) {
+    const int idx = tid + 256 * i, kk = 2 * (idx % 16), pp = idx / 16;
+    tb[kk][pp] = x[i].x;
+    tb[kk + 1][pp] = x[i].y;
   }
   __syncthreads();
   const int q = row >> 1, c = row & 1;
   const Prime& P = ps.p[l];
   const uint64_t nq = 0 - P.q;
-  for (int idx = tid; idx < 64 * 32; idx += 256) {
-    const int pp = idx % 64, kk = idx / 64;
+  // two consecutive slots per 16-byte store
+  for (int idx = tid; idx < 32 * 32; idx += 256) {
+    const int pp = 2 * (idx % 32), kk = idx / 32;
     if (k0 + kk < C) {
-      const uint64_t r = shoup_approx(tb[kk][pp], 1, P.one, nq);  // [0, 4q)
-      __builtin_nontemporal_store(csub(csub(r, 2 * P.q), P.q),
-                                  ct + ((((size_t)q * C + k0 + kk) * 2 + c) * L + l) * N + p0 + pp);
+      const uint64_t r0 = shoup_approx(tb[kk][pp], 1, P.one, nq);  // [0, 4q)
+      const uint64_t r1 = shoup_approx(tb[kk][pp + 1], 1, P.one, nq);
+      const u64x2v v = {csub(csub(r0, 2 * P.q), P.q), csub(csub(r1, 2 * P.q), P.q)};
+      __builtin_nontemporal_store(
+          v, reinterpret_cast<u64x2v*>(
+                 ct + ((((size_t)q * C + k0 + kk) * 2 + c) * L + l) * N + p0 + pp));
     }
   }
 }
