@@ -33,13 +33,16 @@ struct TwSet {
 
 // Constants of the exact fold of the int8 matrix-core digit sums of one limb:
 // a sum V = g0 + g1 2^32 + h 2^64 of signed 64-bit parts is reduced as
-// (g0 + offa) + [ (g1 + offa) 2^32 ] + [ (h + offb) 2^64 ]  (mod q).
+// (g0 + offa) + [ (g1 + offa) 2^32 ] + [ (h + offb) 2^64 ]  (mod q), or, when
+// q = 2^54 - delta with 0 < delta < 2^22, with 2^54 = delta (mod q) alone.
 struct DigitConst {
   uint64_t w32, w32p;  // 2^32 mod q and its Shoup companion
   uint64_t w64, w64p;  // 2^64 mod q and its Shoup companion
   uint64_t offa;       // smallest multiple of q >= 2^53
   uint64_t offb;       // smallest multiple of q >= 2^57
   uint64_t nq;         // 2^64 - q
+  uint64_t twoq;       // 2 q
+  int32_t delta;       // 2^54 - q if that is in (0, 2^22), else 0
 };
 
 struct DigitSet {

@@ -12,9 +12,11 @@
 //     sum_i x y = sum_{s=0}^{12} 256^s S_s,   S_s = sum_{a+b=s} sum_i x_a[i] y_b[i],
 // where every S_s is an exact int32 sum of int8 products (|S_s| < 7 2^14 Dp),
 // which is what the int8 MFMA computes: 49 digit-pair products per residue
-// pair, 13 accumulators per output.  The S_s are folded into a residue in
-// [0, q_l) with 64-bit integer steps and Shoup products.  Nothing here is
-// approximate: the result equals the one of the 64-bit vector kernels.
+// pair, 13 accumulators per output.  The S_s are folded into a value below
+// 2^58 congruent to the sum (signed 32 x 32 -> 64-bit multiply-adds, and
+// either 2^54 = delta (mod q_l) when q_l = 2^54 - delta with a small delta, or
+// Shoup products), which the sums transpose reduces to [0, q_l).  Nothing here
+// is approximate: the result equals the one of the 64-bit vector kernels.
 //
 // Layouts (Dp = d rounded up to a multiple of 32, Dq = d rounded up to a
 // multiple of 64; the contraction runs in steps of 64 coordinates and, when
@@ -177,6 +179,39 @@ __device__ __forceinline__ uint64_t fold_digit_sums(const int32_t (&S)[13],
          shoup_approx(x2, D.w64, D.w64p, D.nq);  // < 2^55 + 8q < 2^58
 }
 
+// The same value for q = 2^54 - delta, 0 < delta < 2^22, without Shoup
+// products (Dp <= 128, so |S_s| < 7 2^21 and |S_12| <= 2^19, as x_6, y_6 lie in
+// [0, 64]).  With 2^54 = delta (mod q):
+//   g0 = 2q + S0 + S1 2^8 + S2 2^16 + S3 2^24     |g0 - 2q| < 2^48
+//   g1 = S4 + ... + S7 2^24,  h = S8 + ... + S11 2^24 + S12 2^32,  |h| < 2^52
+// and V = g0 - 2q + 2^32 (g1 + 2^32 h).  Splitting h = 2^22 hh + hl
+// (0 <= hl < 2^22):  2^32 h = 2^32 hl + 2^54 hh = 2^32 hl + delta hh, so
+// V = g0 + 2^32 z (mod q) with z = g1 + 2^32 hl + delta hh in (-2^52, 2^54.2).
+// Splitting z = 2^24 zh + zl (0 <= zl < 2^24, |zh| < 2^31):  2^32 z = 2^32 zl
+// + 2^56 zh = 2^32 zl + 4 delta zh, and the result g0 + 2^32 zl + 4 delta zh
+// lies in [0, 2^57).  Every product is one signed 32 x 32 -> 64-bit
+// multiply-add.
+__device__ __forceinline__ uint64_t fold_digit_sums_pm(const int32_t (&S)[13],
+                                                       const DigitConst& D, int32_t k1,
+                                                       int32_t k8, int32_t k16, int32_t k24) {
+  auto group = [&](int s, int64_t base) {
+    int64_t g = base + (int64_t)S[s] * k1;
+    g += (int64_t)S[s + 1] * k8;
+    g += (int64_t)S[s + 2] * k16;
+    g += (int64_t)S[s + 3] * k24;
+    return g;
+  };
+  const int64_t h = group(8, 0) + (int64_t)((uint64_t)(uint32_t)S[12] << 32);
+  const int32_t hh = (int32_t)(uint32_t)((uint64_t)h >> 22);
+  const uint32_t hl = (uint32_t)h & 0x3fffffu;
+  const int64_t z = group(4, 0) + (int64_t)D.delta * hh + (int64_t)((uint64_t)hl << 32);
+  const int32_t zh = (int32_t)(uint32_t)((uint64_t)z >> 24);
+  const uint32_t zl = (uint32_t)z & 0xffffffu;
+  const int64_t r = group(0, (int64_t)D.twoq) + (int64_t)(4 * D.delta) * zh +
+                    (int64_t)((uint64_t)zl << 32);
+  return (uint64_t)r;
+}
+
 // One MFMA step of the contraction: 64 coordinates (16 bytes per lane,
 // v_mfma_i32_16x16x64_i8) or 32 (8 bytes per lane, v_mfma_i32_16x16x32_i8,
 // lane l supplying row or column l % 16 and contraction bytes 8 (l / 16) ..
@@ -219,7 +254,7 @@ __device__ __forceinline__ v4i mfma_digits(typename StepFrag<W32>::T a,
 // around each barrier keep them behind it.  Workgroups are numbered so that
 // the tiles of one slot range run back to back on one XCD, which shares the
 // operands in its L2.
-template <int DP>
+template <int DP, bool PM>
 __global__ void __launch_bounds__(256, 3)
 k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R, int C, int L,
              int logN, int n_items, DigitSet ds, uint64_t* __restrict__ sums) {
@@ -233,6 +268,7 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
   constexpr int BR = (BU + 255) / 256;  // DMA rounds of the 256 threads
   static_assert(BR * 256 * 16 + (kMfmaChunks - H) * Sk <= (int)kMfmaDbSlack,
                 "a stage's DMA stays inside the digit region's slack");
+  static_assert(!PM || Dp <= 128, "the bounds of the short fold hold for Dp <= 128");
   __shared__ uint4 sb0[BR * 256], sb1[BR * 256];
   const int N = 1 << logN;
   const int per_xcd = (n_items + 7) >> 3;
@@ -249,6 +285,9 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
   const int wrow0 = rt * kMfmaRows + 16 * w;
   const int arow = wrow0 + m16 < R ? wrow0 + m16 : R - 1;
   const DigitConst& D = ds.c[l];
+  // opaque 1, 2^8, 2^16, 2^24: the fold's terms become 64-bit multiply-adds
+  const int32_t k1 = opaque_i32(1), k8 = opaque_i32(1 << 8), k16 = opaque_i32(1 << 16),
+                k24 = opaque_i32(1 << 24);
   auto stage = [&](int p, int cq, uint4* buf) {
     const uint4* src = reinterpret_cast<const uint4*>(
         dbd + (((size_t)l * N + p) * C + k0 + cq * H) * Sk);
@@ -326,7 +365,7 @@ k_mac_mfma(const int8_t* __restrict__ qd, const int8_t* __restrict__ dbd, int R,
       int32_t S[13];
 #pragma unroll
       for (int s2 = 0; s2 < 13; ++s2) S[s2] = acc[s2][e];
-      v[e] = fold_digit_sums(S, D);
+      v[e] = PM ? fold_digit_sums_pm(S, D, k1, k8, k16, k24) : fold_digit_sums(S, D);
     }
     __builtin_amdgcn_sched_barrier(0);
     // the DMA into nxt: older than the fragment loads of a last stage
@@ -478,8 +517,15 @@ static void launch_mac_mfma_t(const int8_t* qd, const int8_t* dbd, int R, int C,
   const long n_items = (long)L * (N / kMfmaSlots) * ((R + kMfmaRows - 1) / kMfmaRows) *
                        ((C + kMfmaChunks - 1) / kMfmaChunks);
   const long per_xcd = (n_items + 7) >> 3;
-  hipLaunchKernelGGL(k_mac_mfma<DP>, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, st, qd, dbd,
-                     R, C, L, logN, (int)n_items, ds, sums);
+  // the short fold when every prime is 2^54 - delta with a small delta
+  bool pm = true;
+  for (int l = 0; l < L; ++l) pm = pm && ds.c[l].delta != 0;
+  if (pm)
+    hipLaunchKernelGGL((k_mac_mfma<DP, true>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, st,
+                       qd, dbd, R, C, L, logN, (int)n_items, ds, sums);
+  else
+    hipLaunchKernelGGL((k_mac_mfma<DP, false>), dim3((unsigned)(per_xcd * 8)), dim3(256), 0, st,
+                       qd, dbd, R, C, L, logN, (int)n_items, ds, sums);
 }
 
 hipError_t launch_mac_mfma(const int8_t* qd, const int8_t* dbd, int Q, int d, int C, int L,

@@ -159,6 +159,9 @@ DigitConst digit_consts(uint64_t q) {
   D.offa = (((1ull << 53) + q - 1) / q) * q;
   D.offb = (((1ull << 57) + q - 1) / q) * q;
   D.nq = 0 - q;
+  D.twoq = 2 * q;
+  const uint64_t two54 = 1ull << 54;
+  D.delta = (q < two54 && two54 - q < (1ull << 22)) ? (int32_t)(two54 - q) : 0;
   return D;
 }
 

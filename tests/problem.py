@@ -43,10 +43,12 @@ class Problem:
 
 def make_problem(N: int, L: int, t_bits: int, n: int, d: int, Q: int, dtype: str = "u8",
                  seed: int = 0, points: Optional[np.ndarray] = None,
-                 queries: Optional[np.ndarray] = None, t: Optional[int] = None) -> Problem:
+                 queries: Optional[np.ndarray] = None, t: Optional[int] = None,
+                 qs: Optional[Sequence[int]] = None) -> Problem:
     """t: the plain modulus (default: the prime of t_bits bits that the
-    workloads use)."""
-    P = oracle.Params(N, oracle.rns_primes(N, L),
+    workloads use); qs: the RNS primes (default: the L largest NTT-friendly
+    primes below 2^54)."""
+    P = oracle.Params(N, list(qs) if qs is not None else oracle.rns_primes(N, L),
                       t if t is not None else oracle.plain_modulus(N, t_bits))
     g = np.random.default_rng(seed)
     if points is None:

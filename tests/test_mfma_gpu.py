@@ -132,6 +132,25 @@ def test_power_of_two_t(stage, dt):
     assert (vo == out).all() and (vs == share).all()
 
 
+@pytest.mark.parametrize("bits", [(50, 50), (54, 50), (54, 52)])
+def test_primes_away_from_2_54(stage, bits):
+    """The fold of the digit sums has two forms: a short one that uses
+    2^54 = delta (mod q) when every prime is 2^54 - delta with delta < 2^22
+    (the primes the workloads use), and a general one with Shoup products.
+    Primes of 50 and 52 bits, alone or beside a prime just below 2^54, take
+    the general form; both agree with the oracle and the vector schedule."""
+    from paper_1904_02033_amd import native as nat
+    N = 4096
+    qs = [oracle.rns_primes(N, i + 1, bits=b)[i] for i, b in enumerate(bits)]
+    assert any((1 << 54) - q >= 1 << 22 for q in qs)
+    pb = make_problem(N, 2, 25, 2 * N + 51, 100, 5, "i8", seed=43, qs=qs)
+    ctx, db, sk, ct, qids = _setup(stage, pb)
+    out, share = _run(stage, ctx, db, pb, ct, qids, nat.SANNS_MODE_BATCHED, MFMA)
+    _check_rows(stage, pb, ctx, sk, out, share, range(pb.Q * pb.C), n_coeffs=8)
+    vo, vs = _run(stage, ctx, db, pb, ct, qids, nat.SANNS_MODE_FUSED, 22)
+    assert (vo == out).all() and (vs == share).all()
+
+
 def test_mfma_many_tiles_equals_vector_schedule(stage):
     """66 rows (two row tiles, the second with 2 rows) x 33 chunks (two chunk
     tiles, the second with one chunk), d = 128: every output equal to the
