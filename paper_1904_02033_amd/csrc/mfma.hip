@@ -453,13 +453,21 @@ k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R
   const int q = row >> 1, c = row & 1;
   const Prime& P = ps.p[l];
   const uint64_t nq = 0 - P.q;
+  // x < 2^58 -> [0, q): for q = 2^54 - delta with delta < 2^22 by 2^54 =
+  // delta (mod q) (x mod 2^54 + (x >> 54) delta < 2^54 + 2^26 < 2q), else by
+  // a Shoup product by 1 (to [0, 4q)) and two conditional subtractions
+  const uint64_t two54 = 1ull << 54;
+  const bool pm = P.q < two54 && two54 - P.q < (1ull << 22);
+  const uint64_t delta = two54 - P.q;
+  auto reduce = [&](uint64_t x) -> uint64_t {
+    if (pm) return csub((x & (two54 - 1)) + (x >> 54) * delta, P.q);
+    return csub(csub(shoup_approx(x, 1, P.one, nq), 2 * P.q), P.q);
+  };
   // two consecutive slots per 16-byte store
   for (int idx = tid; idx < 32 * 32; idx += 256) {
     const int pp = 2 * (idx % 32), kk = idx / 32;
     if (k0 + kk < C) {
-      const uint64_t r0 = shoup_approx(tb[kk][pp], 1, P.one, nq);  // [0, 4q)
-      const uint64_t r1 = shoup_approx(tb[kk][pp + 1], 1, P.one, nq);
-      const u64x2v v = {csub(csub(r0, 2 * P.q), P.q), csub(csub(r1, 2 * P.q), P.q)};
+      const u64x2v v = {reduce(tb[kk][pp]), reduce(tb[kk][pp + 1])};
       __builtin_nontemporal_store(
           v, reinterpret_cast<u64x2v*>(
                  ct + ((((size_t)q * C + k0 + kk) * 2 + c) * L + l) * N + p0 + pp));
