@@ -44,7 +44,7 @@ __device__ __forceinline__ uint64_t mulmod(uint64_t a, uint64_t b, const Prime& 
 //      r = 2q + c (R = 2Q) for polynomial p = ((q d + i) 2 + c) L + l: each
 //      32-slot group of a row is one contiguous block over the coordinates,
 //      the form the digit transpose of the matrix-core schedule reads.
-template <int LOGN, int SPLIT>
+template <int LOGN, int SPLIT, bool PM = false>
 __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
                                              const uint64_t* __restrict__ in,
                                              uint64_t* __restrict__ out, int L,
@@ -62,7 +62,7 @@ __device__ __forceinline__ void ntt_fwd_poly(int p, int tid, uint64_t* lds,
     bad |= v[a] >= P.q;
   }
   if (bad && err) atomicOr(err, 1u);
-  ntt_fwd<LOGN>(v, lds, tid, tws.tw[l], P);
+  ntt_fwd<LOGN, PM>(v, lds, tid, tws.tw[l], P);
   uint64_t* dst = out + (size_t)p * N;
   if constexpr (SPLIT == 2) {
     const int c = (p / L) & 1, i = (p / (2 * L)) % d, q = p / (2 * L * d);
@@ -101,13 +101,13 @@ constexpr int intt_mask_waves(int logn) {
   return logn == 11 || logn == 12 || logn == 14 ? 4 : 6;
 }
 
-// One polynomial per workgroup.
-template <int LOGN, int SPLIT>
+// One polynomial per workgroup (PM: every prime is 2^54 - delta, delta < 2^22).
+template <int LOGN, int SPLIT, bool PM = false>
 __global__ void __launch_bounds__(NttShape<LOGN>::T, ntt_fwd_waves(LOGN, SPLIT))
 k_ntt_fwd(const uint64_t* __restrict__ in, uint64_t* __restrict__ out, int L, PrimeSet ps,
           TwSet tws, uint32_t* err, int d, int R) {
   extern __shared__ uint64_t lds[];
-  ntt_fwd_poly<LOGN, SPLIT>(blockIdx.x, threadIdx.x, lds, in, out, L, ps, tws, err, d, R);
+  ntt_fwd_poly<LOGN, SPLIT, PM>(blockIdx.x, threadIdx.x, lds, in, out, L, ps, tws, err, d, R);
 }
 
 // In-place inverse transform, result multiplied by N^-1 and in [0, q).
@@ -1562,10 +1562,15 @@ hipError_t launch_ntt_fwd(const uint64_t* in, uint64_t* out, int n_polys, int lo
                           hipStream_t st, int d, int R) {
   if (n_polys <= 0) return hipSuccess;
   if (split == 2 && (logN < 5 || d <= 0 || n_polys != R * d * L)) return hipErrorInvalidValue;
+  bool pm = true;  // the matrix-core schedule's form: the short last reduction when it holds
+  for (int l = 0; l < L; ++l) pm = pm && pm_delta(ps.p[l].q) != 0;
   switch (logN) {
 #define SANNS_CASE(LG)                                                                    \
   case LG:                                                                                \
-    if (split == 2)                                                                       \
+    if (split == 2 && pm)                                                                 \
+      ntt_launch<LG>(k_ntt_fwd<LG, 2, true>, (unsigned)n_polys, st, in, out, L, ps, tws, err, \
+                     d, R);                                                               \
+    else if (split == 2)                                                                  \
       ntt_launch<LG>(k_ntt_fwd<LG, 2>, (unsigned)n_polys, st, in, out, L, ps, tws, err, d, R); \
     else if (split == 1)                                                                  \
       ntt_launch<LG>(k_ntt_fwd<LG, 1>, (unsigned)n_polys, st, in, out, L, ps, tws, err, d, R); \

@@ -454,13 +454,11 @@ k_sums_to_ct(const uint64_t* __restrict__ sums, uint64_t* __restrict__ ct, int R
   const Prime& P = ps.p[l];
   const uint64_t nq = 0 - P.q;
   // x < 2^58 -> [0, q): for q = 2^54 - delta with delta < 2^22 by 2^54 =
-  // delta (mod q) (x mod 2^54 + (x >> 54) delta < 2^54 + 2^26 < 2q), else by
-  // a Shoup product by 1 (to [0, 4q)) and two conditional subtractions
-  const uint64_t two54 = 1ull << 54;
-  const bool pm = P.q < two54 && two54 - P.q < (1ull << 22);
-  const uint64_t delta = two54 - P.q;
+  // delta (mod q), else by a Shoup product by 1 (to [0, 4q)) and two
+  // conditional subtractions
+  const uint32_t pd = pm_delta(P.q);
   auto reduce = [&](uint64_t x) -> uint64_t {
-    if (pm) return csub((x & (two54 - 1)) + (x >> 54) * delta, P.q);
+    if (pd) return reduce_pm60(x, pd, P.q);
     return csub(csub(shoup_approx(x, 1, P.one, nq), 2 * P.q), P.q);
   };
   // two consecutive slots per 16-byte store

@@ -88,6 +88,20 @@ __device__ __forceinline__ uint64_t reduce64(uint64_t x, uint64_t one, uint64_t 
   return csub(r, q);
 }
 
+// delta when q = 2^54 - delta with 0 < delta < 2^22, else 0.
+__host__ __device__ inline uint32_t pm_delta(uint64_t q) {
+  const uint64_t two54 = 1ull << 54;
+  return (q < two54 && two54 - q < (1ull << 22)) ? (uint32_t)(two54 - q) : 0u;
+}
+
+// x mod q for x < 2^60 and q = 2^54 - delta, delta = pm_delta(q) != 0: with
+// 2^54 = delta (mod q), x mod 2^54 + (x >> 54) delta < 2^54 + 2^28 < 2q, then
+// one conditional subtraction.
+__device__ __forceinline__ uint64_t reduce_pm60(uint64_t x, uint32_t delta, uint64_t q) {
+  const uint64_t r = (uint64_t)(uint32_t)(x >> 54) * delta + (x & ((1ull << 54) - 1));
+  return csub(r, q);
+}
+
 __device__ __forceinline__ uint64_t addmod(uint64_t a, uint64_t b, uint64_t q) {
   return csub(a + b, q);
 }

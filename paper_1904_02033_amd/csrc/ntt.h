@@ -217,15 +217,19 @@ __device__ __forceinline__ void inv_from(uint64_t (&v)[16], uint64_t* lds, int t
 // Forward transform.  Input: residues below q, slot a = coefficient
 // coef_index(tid, a).  Output: slot a = evaluation a + 16 tid in [0, q).
 // lds holds NttShape<LOGN>::lds_bytes; the caller synchronises before reusing it.
-template <int LOGN>
+// PM: q = 2^54 - delta with delta = pm_delta(q) != 0 (the last reduction by
+// 2^54 = delta (mod q) instead of a Shoup product).
+template <int LOGN, bool PM = false>
 __device__ __forceinline__ void ntt_fwd(uint64_t (&v)[16], uint64_t* lds, int tid,
                                         const u64x2* __restrict__ tw, const Prime& P) {
   static_assert(LOGN <= 14, "forward values must stay below 2^60");
   fwd_from<LOGN, 0>(v, lds, tid, tw, P.q);
   const uint64_t nq = 0 - P.q;
+  const uint32_t pd = pm_delta(P.q);
 #pragma unroll
   for (int a = 0; a < 16; ++a)
-    v[a] = csub(csub(shoup_approx(v[a], 1, P.one, nq), 2 * P.q), P.q);
+    v[a] = PM ? reduce_pm60(v[a], pd, P.q)
+              : csub(csub(shoup_approx(v[a], 1, P.one, nq), 2 * P.q), P.q);
 }
 
 // Inverse transform.  Input: residues below q, slot a = evaluation a + 16 tid

@@ -160,8 +160,7 @@ DigitConst digit_consts(uint64_t q) {
   D.offb = (((1ull << 57) + q - 1) / q) * q;
   D.nq = 0 - q;
   D.twoq = 2 * q;
-  const uint64_t two54 = 1ull << 54;
-  D.delta = (q < two54 && two54 - q < (1ull << 22)) ? (int32_t)(two54 - q) : 0;
+  D.delta = (int32_t)pm_delta(q);
   return D;
 }
 
