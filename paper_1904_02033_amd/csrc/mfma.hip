@@ -80,12 +80,16 @@ __device__ __forceinline__ uint32_t gather_byte(uint64_t y0, uint64_t y1, uint64
 // Dp bytes (16 bytes per store, zero digits past coordinate d; two threads
 // share a slot's 16-coordinate group, one for digits 0-3, one for 4-6).  The
 // query side is read and written with nontemporal hints: it is touched once.
+// LDS word (i, pp) sits at i (S + 1) + pp + i / 16: the extra word per 16
+// coordinates puts the 16-coordinate groups that the lanes of one read
+// instruction take on different banks (without it, eight of them share one).
 template <bool DB, int S>
 __global__ void __launch_bounds__(16 * S)
 k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, int d, int Dp,
             int L, int logN, int C, int Sk) {
-  extern __shared__ uint64_t lw[];  // [Dp][S + 1]
+  extern __shared__ uint64_t lw[];  // Dp (S + 1) + Dp / 16 words
   constexpr int P1 = S + 1, NT = 16 * S;
+  auto at = [&](int i, int pp) { return i * P1 + pp + (i >> 4); };
   const int N = 1 << logN;
   const int groups = N / S;
   int b = blockIdx.x;
@@ -103,7 +107,7 @@ k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, i
             src)[(((size_t)l * C + ent) * d + i) * N + p0 + pp];
         x = (uint64_t)h.x + ((uint64_t)h.y << 27);
       }
-      lw[i * P1 + pp] = digit_word(x);
+      lw[at(i, pp)] = digit_word(x);
     }
   } else {
     // two consecutive slots of a coordinate per 16-byte load
@@ -119,8 +123,8 @@ k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, i
                 kDigitGroup +
             pq % kDigitGroup));
       }
-      lw[i * P1 + pp] = digit_word(x.x);
-      lw[i * P1 + pp + 1] = digit_word(x.y);
+      lw[at(i, pp)] = digit_word(x.x);
+      lw[at(i, pp) + 1] = digit_word(x.y);
     }
   }
   __syncthreads();
@@ -131,7 +135,7 @@ k_to_digits(const void* __restrict__ src, int8_t* __restrict__ dst, int n_ent, i
     const int p = p0 + pp;
     uint64_t y[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) y[j] = lw[(16 * cg + j) * P1 + pp];
+    for (int j = 0; j < 16; ++j) y[j] = lw[at(16 * cg + j, pp)];
     int8_t* row = DB ? dst + (((size_t)l * N + p) * C + ent) * Sk
                      : dst + (((size_t)l * N + p) * n_ent + ent) * (size_t)(7 * Dp);
 #pragma unroll
@@ -499,7 +503,7 @@ hipError_t launch_query_digits(const uint64_t* qntt, int8_t* qd, int Q, int d, i
   constexpr int S = kQueryDigitSlots;
   const long nb = (long)L * 2 * Q * (N / S);
   if (nb <= 0) return hipSuccess;
-  const size_t lds = (size_t)Dp * (S + 1) * sizeof(uint64_t);
+  const size_t lds = ((size_t)Dp * (S + 1) + Dp / 16) * sizeof(uint64_t);
   hipLaunchKernelGGL((k_to_digits<false, S>), dim3((unsigned)nb), dim3(16 * S), lds, st,
                      (const void*)qntt, qd, 2 * Q, d, Dp, L, logN, 0, 0);
   return hipGetLastError();
@@ -510,7 +514,7 @@ hipError_t launch_db_digits(const uint2* dbres, int8_t* dbd, int C, int d, int L
   const int Dp = mfma_padded_d(d), N = 1 << logN;
   const long nb = (long)L * C * (N / 32);
   if (nb <= 0) return hipSuccess;
-  const size_t lds = (size_t)Dp * (32 + 1) * sizeof(uint64_t);
+  const size_t lds = ((size_t)Dp * (32 + 1) + Dp / 16) * sizeof(uint64_t);
   hipLaunchKernelGGL((k_to_digits<true, 32>), dim3((unsigned)nb), dim3(512), lds, st,
                      (const void*)dbres, dbd, C, d, Dp, L, logN, C, mfma_db_stride(d));
   return hipGetLastError();
