@@ -250,17 +250,24 @@ __device__ __forceinline__ uint64_t lift_small(int x, uint64_t q) {
 }
 
 // (X mod 2^(b+1)) - 2^b  mod q, X the 256-bit little-endian integer w[0..7]:
-// Horner over the 32-bit words from the top kept word down (r 2^32 by a
-// Shoup product with 2^32 mod q; q > 2^32 keeps r + w below 2q).
+// Horner over the 32-bit words from the top kept word down.  r 2^32 is a
+// Shoup product with 2^32 mod q (q > 2^32 keeps r + w below 2q), or, for q =
+// 2^54 - delta with delta < 2^22, (r >> 22) delta + (r mod 2^22) 2^32 (as
+// 2^54 = delta mod q; below 2^55 with r < 2^54), reduced with w added.
 __device__ __forceinline__ uint64_t flood_residue(const uint32_t* w, int b, uint64_t twob,
                                                   const DigitConst& D, uint64_t q) {
   const int bits = b + 1;
+  const uint32_t pd = pm_delta(q);
   uint64_t r = 0;
   for (int i = (bits - 1) >> 5; i >= 0; --i) {
     const int keep = bits - 32 * i;
     const uint32_t x = keep >= 32 ? w[i] : (w[i] & ((1u << keep) - 1u));
-    r = shoup(r, D.w32, D.w32p, q) + x;
-    if (r >= q) r -= q;
+    if (pd) {
+      r = reduce_pm60((uint64_t)(uint32_t)(r >> 22) * pd + ((r & 0x3fffffull) << 32) + x, pd, q);
+    } else {
+      r = shoup(r, D.w32, D.w32p, q) + x;
+      if (r >= q) r -= q;
+    }
   }
   return submod(r, twob, q);
 }

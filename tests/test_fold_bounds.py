@@ -7,7 +7,8 @@ step for step as the device code takes them:
   2^19 for d <= 128) into a value below 2^57 congruent to V;
 * x mod 2^54 + (x >> 54) delta, one conditional subtraction, for x < 2^60
   (the sums transpose, values below 2^58; the last step of the query
-  transform, values below 2^60).
+  transform, values below 2^60);
+* the Horner step of the circuit-private form's flood residues.
 
 Extreme diagonals (every sum at +bound or -bound, alternating signs, the
 largest top sum) and random ones, for every such prime of the ring degrees
@@ -107,6 +108,22 @@ def test_short_reduction_below_2_60():
               (1 << 60) - 1] + [rng.randrange(1 << 60) for _ in range(2000)]
         for x in xs:
             assert reduce_short(x, q) == x % q, (q, x)
+
+
+def test_short_horner_step():
+    """The flood's Horner step r -> r 2^32 + w (mod q) of the circuit-private
+    form: (r >> 22) delta + (r mod 2^22) 2^32 + w < 2^56, then the short
+    reduction."""
+    for q in _short_primes():
+        delta = (1 << 54) - q
+        rng = random.Random(q + 2)
+        cases = [(0, 0), (q - 1, (1 << 32) - 1), (q - 1, 0), ((1 << 22) - 1, 1)]
+        cases += [(rng.randrange(q), rng.randrange(1 << 32)) for _ in range(2000)]
+        for r, w in cases:
+            assert (r >> 22) < 1 << 32
+            y = (r >> 22) * delta + ((r & 0x3FFFFF) << 32) + w
+            assert y < 1 << 56
+            assert reduce_short(y, q) == (r * (1 << 32) + w) % q, (q, r, w)
 
 
 def test_workload_primes_take_the_short_forms():
