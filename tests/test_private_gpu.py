@@ -120,6 +120,32 @@ def test_private_form_matches_oracle(mods, case):
     ctx.close()
 
 
+def test_private_form_primes_away_from_2_54(mods):
+    """50-bit primes take the general form of the flood residues' Horner
+    step (a Shoup product by 2^32 mod q; primes 2^54 - delta with delta <
+    2^22 take the short one): every output still equals the oracle's."""
+    nat, stage = mods
+    N = 1024
+    qs = [oracle.rns_primes(N, i + 1, bits=50)[i] for i in range(2)]
+    pb = make_problem(N, 2, 20, 2 * N + 13, 7, 2, "u8", seed=631, qs=qs)
+    ctx, db, sk, ct, qids = _setup(nat, stage, pb)
+    b = nat.sanns_flood_bits(ctx.handle)
+    assert b == oracle.flood_bits(pb.P) and b > 32
+    pks, pkd = _public_keys(stage, ctx, pb, sk, 900)
+    C = db.n_chunks
+    D = stage.Distances(ctx, db, pb.Q, mode=nat.SANNS_MODE_FUSED, private=True)
+    out, share = D.run(ct, pb.key, qids, pk=pkd)
+    torch.cuda.synchronize()
+    ctx.device_status()
+    M = pb.Q * C
+    want = _oracle_rows(pb, pks, [(m, divmod(m, C)) for m in range(M)], b, {})
+    for m, (w_ct, w_r) in want.items():
+        assert (out[m].cpu().numpy() == w_ct).all(), m
+        assert (share[m].cpu().numpy() == w_r).all(), m
+    _check_shares(stage, ctx, pb, sk, out, share, [divmod(m, C) for m in range(M)])
+    ctx.close()
+
+
 def test_private_form_matrix_cores_and_work_lists(mods):
     """The matrix-core schedule and a work list give the oracle's outputs
     too, and a smaller flood width is honoured."""
