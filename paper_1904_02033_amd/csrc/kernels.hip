@@ -420,7 +420,8 @@ __device__ __forceinline__ MacTile<QT, CT> regular_tile(int y, int Q, int C) {
 }
 
 // WIDE = false: d <= 255, a single accumulation without folded partials.
-template <int QT, int CT, bool WIDE = true>
+// NT: the database is streamed with nontemporal loads (read once per launch).
+template <int QT, int CT, bool WIDE = true, bool NT = false>
 __device__ __forceinline__ void mac_reg_slot(const MacTile<QT, CT>& T, int s, int l,
                                              const uint2* __restrict__ qntt,
                                              const uint2* __restrict__ db, int d, int L, int N,
@@ -470,8 +471,17 @@ __device__ __forceinline__ void mac_reg_slot(const MacTile<QT, CT>& T, int s, in
         x1[a][c] = v.y;
         x01[a][c] = v.x + v.y;
       }
+    auto db_load = [&](const uint2* ptr) -> uint2 {
+      if constexpr (NT) {
+        const uint64_t v =
+            __builtin_nontemporal_load(reinterpret_cast<const unsigned long long*>(ptr));
+        return make_uint2(lo32(v), hi32(v));
+      } else {
+        return *ptr;
+      }
+    };
 #pragma unroll
-    for (int b = 0; b < CT; ++b) yv[b] = dbb[b][i0 * dbstride_i];
+    for (int b = 0; b < CT; ++b) yv[b] = db_load(dbb[b] + i0 * dbstride_i);
     for (int i = i0; i < i1; ++i) {
       const int inext = i + 1 < i1 ? i + 1 : i;
       uint2 xn[QT][2];
@@ -481,7 +491,7 @@ __device__ __forceinline__ void mac_reg_slot(const MacTile<QT, CT>& T, int s, in
 #pragma unroll
         for (int c = 0; c < 2; ++c) xn[a][c] = qb[a][inext * qstride_i + (size_t)c * L * N];
 #pragma unroll
-      for (int b = 0; b < CT; ++b) yn[b] = dbb[b][inext * dbstride_i];
+      for (int b = 0; b < CT; ++b) yn[b] = db_load(dbb[b] + inext * dbstride_i);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int b = 0; b < CT; ++b) {
@@ -536,7 +546,9 @@ __device__ __forceinline__ void mac_reg_slot(const MacTile<QT, CT>& T, int s, in
 // range and reuse that group's query operands from its L2.  The all-pairs
 // schedule keeps the slot range fastest, which streams each database row
 // contiguously (measured faster for a single query).
-template <int QT, int CT>
+// NT (the all-pairs schedule, no tile table): each database residue is read
+// once per launch, so it is streamed with nontemporal loads.
+template <int QT, int CT, bool NT>
 __global__ void __launch_bounds__(256)
 k_mac(const uint2* __restrict__ qntt, const uint2* __restrict__ db,
       const MacTile<QT, CT>* __restrict__ tiles, int n_tiles, int Q, int d, int L, int logN,
@@ -558,8 +570,8 @@ k_mac(const uint2* __restrict__ qntt, const uint2* __restrict__ db,
     l = lin / nsr / n_tiles;
   }
   const MacTile<QT, CT> T = tiles ? tiles[y] : regular_tile<QT, CT>(y, Q, C);
-  mac_reg_slot<QT, CT>(T, sr * blockDim.x + threadIdx.x, l, qntt, db, d, L, 1 << logN, C, ps,
-                       out);
+  mac_reg_slot<QT, CT, true, NT>(T, sr * blockDim.x + threadIdx.x, l, qntt, db, d, L, 1 << logN,
+                                 C, ps, out);
 }
 
 // LDS-staged multiply-accumulate for the every-query-against-every-chunk
@@ -1646,8 +1658,14 @@ static hipError_t launch_mac_t(const uint2* qntt, const uint2* db, const void* t
   const int bs = N < 256 ? N : 256;
   const long nb = (long)(N / bs) * n_tiles * L;
   const long per_xcd = (nb + 7) >> 3;
-  hipLaunchKernelGGL((k_mac<QT, CT>), dim3((unsigned)(per_xcd * 8)), dim3(bs), 0, st, qntt, db,
-                     (const MacTile<QT, CT>*)tiles, n_tiles, Q, d, L, logN, C, (int)nb, ps, out);
+  if (tiles)
+    hipLaunchKernelGGL((k_mac<QT, CT, false>), dim3((unsigned)(per_xcd * 8)), dim3(bs), 0, st,
+                       qntt, db, (const MacTile<QT, CT>*)tiles, n_tiles, Q, d, L, logN, C,
+                       (int)nb, ps, out);
+  else
+    hipLaunchKernelGGL((k_mac<QT, CT, true>), dim3((unsigned)(per_xcd * 8)), dim3(bs), 0, st,
+                       qntt, db, (const MacTile<QT, CT>*)tiles, n_tiles, Q, d, L, logN, C,
+                       (int)nb, ps, out);
   return hipGetLastError();
 }
 
